@@ -1,0 +1,187 @@
+/*
+ * tetmf.h -- matrix-free finite-element operators on uniformly refined
+ * macro-tetrahedra, for AMD Instinct MI355X (gfx950).
+ *
+ * The library computes y = A x for operators defined by a weak form on a
+ * coarse (macro) tetrahedral mesh refined uniformly `level` times, without
+ * assembling A.  Equation (4.1) of the paper's section "Matrix-Free Finite
+ * Elements" defines the operation: A = sum_T P_T A_T R_T over all
+ * micro-tetrahedra T, with A_T the local matrix of the integrand on T
+ * (algorithm "LocalApply").  Section "Hybrid Tetrahedral Grids" defines the
+ * mesh: each macro-tetrahedron is refined uniformly, every micro-tetrahedron
+ * is a translate of one of six reference shapes, and DoFs are addressed by
+ * implicit structured indices.  Operator kinds:
+ *
+ *   TMF_P1_LAPLACE   int grad(phi_i).grad(phi_j), linear Lagrange  (equation P1)
+ *   TMF_P1_DIVKGRAD  int k grad(phi_i).grad(phi_j), k nodal linear
+ *   TMF_P2_LAPLACE   int grad(phi_i).grad(phi_j), quadratic Lagrange
+ *   TMF_P2_DIVKGRAD  int k grad(phi_i).grad(phi_j), k nodal quadratic (equation P2V)
+ *   TMF_P2V_EPSILON  int 2 mu eps(u):eps(v), eps = sym grad, vector quadratic
+ *                    Lagrange, mu nodal quadratic
+ *
+ * All are positive semi-definite stiffness matrices.  The affine forms are
+ * integrated exactly (the integrand of P2V has degree 4; the kernels use the
+ * exact closed form, which equals any degree-4-exact quadrature up to
+ * rounding).  The epsilon operator on the radially blended shell map is
+ * integrated with the quadrature rule given at operator creation.
+ *
+ * --- Vector layout ("macro-local") -----------------------------------------
+ * The refinement lattice of macro tet (v0,v1,v2,v3) at level l, n = 2^l, is
+ * the set of points (i,j,k), i,j,k >= 0, i+j+k <= N, at parameter position
+ * v0 + (i(v1-v0) + j(v2-v0) + k(v3-v0))/N, integer barycentric coordinates
+ * (N-i-j-k, i, j, k).  P1 DoFs use N = n; P2 DoFs use N = 2n (micro-vertex
+ * p -> 2p, micro-edge (p,q) -> p+q).  Within a macro, point (i,j,k) is stored
+ * at
+ *     idx = C3(N) - C3(N-k) + j(2(N-k)+3-j)/2 + i,   C3(M) = (M+1)(M+2)(M+3)/6
+ * (i fastest, then j, then k); macro m's block starts at m * C3(N).  A DoF on
+ * a face, edge or vertex shared by several macros has one copy per macro.
+ * Vector fields (epsilon operator) are stored component-major: [u_x | u_y | u_z],
+ * each block of length n_local.  Coefficients use the layout of the space
+ * they live in (P1 for TMF_P1_DIVKGRAD, P2 otherwise), one scalar per point.
+ *
+ * Inputs must be consistent (all copies of a DoF equal); outputs are
+ * consistent (the partial sums of the copies are added and every copy gets
+ * the total).  The canonical key of a point, which identifies the copies of
+ * one DoF, is the list of (global vertex id, barycentric integer) pairs with
+ * nonzero integer, sorted by vertex id, padded with (-1, 0): see
+ * tmf_mesh_dof_info.
+ *
+ * --- Boundary condition ----------------------------------------------------
+ * TMF_BC_DIRICHLET_ZERO applies D A D, D the 0/1 mask of DoFs not on the
+ * domain boundary: boundary rows and columns are zero (y_b = 0, x_b ignored).
+ * A DoF is on the domain boundary when one of its copies lies on a macro face
+ * that belongs to a single macro tet.  TMF_BC_NONE applies A.
+ *
+ * --- Ownership, streams, errors --------------------------------------------
+ * Every call returns TMF_OK (0) or a negative code; no exception crosses the
+ * ABI and tmf_last_error() gives a thread-local message for the last failure.
+ * Handles are owned by the library (create / destroy).  Device buffers passed
+ * to apply calls are owned by the caller; they must be device memory of the
+ * current HIP device, aligned to their element type, and must not alias
+ * unless stated.  Apply calls enqueue work on `stream` (a hipStream_t; NULL
+ * = the default stream) and return without synchronising; they allocate
+ * nothing, so they can be captured into a HIP graph.  On an argument error
+ * nothing is enqueued and outputs are untouched.
+ */
+#ifndef TETMF_H
+#define TETMF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int tmf_status;
+#define TMF_OK 0
+#define TMF_EINVAL (-1)        /* invalid argument */
+#define TMF_ENOMEM (-2)        /* host or device allocation failed */
+#define TMF_EDEVICE (-3)       /* HIP runtime error (launch, copy) */
+#define TMF_EUNSUPPORTED (-4)  /* valid but unsupported combination */
+#define TMF_ENOTCONV (-5)      /* iterative solve did not reach its tolerance */
+
+#define TMF_P1_LAPLACE 0
+#define TMF_P1_DIVKGRAD 1
+#define TMF_P2_LAPLACE 2
+#define TMF_P2_DIVKGRAD 3
+#define TMF_P2V_EPSILON 4
+
+#define TMF_F64 0
+#define TMF_F32 1
+
+#define TMF_BC_NONE 0
+#define TMF_BC_DIRICHLET_ZERO 1
+
+/* Geometry map of the macro mesh.  AFFINE: physical = parametric position.
+ * SHELL_RADIAL: physical x = Phi(xi) = xi |xi|_1 / |xi|_2, which maps the
+ * flat faces |xi|_1 = r onto spheres of radius r (every macro tet must lie in
+ * one closed coordinate octant).  Curved elements enter only through the
+ * Jacobian at quadrature points (the curvilinear remark of the tabulation
+ * section). */
+#define TMF_MAP_AFFINE 0
+#define TMF_MAP_SHELL_RADIAL 1
+
+#define TMF_MAX_LEVEL_P1 9
+#define TMF_MAX_LEVEL_P2 8
+#define TMF_MAX_QUAD 64
+
+typedef struct tmf_mesh tmf_mesh;
+typedef struct tmf_op tmf_op;
+typedef struct tmf_batch tmf_batch;
+typedef void *tmf_stream; /* hipStream_t */
+
+/* Library version string and the last error message of this thread. */
+const char *tmf_version(void);
+const char *tmf_last_error(void);
+const char *tmf_status_string(tmf_status s);
+
+/* Create a refined macro mesh.
+ *   vertices  host, nv x 3 doubles (row-major)
+ *   tets      host, nt x 4 vertex ids in [0, nv); the vertex order of a tet
+ *             fixes its lattice (vertex 0 = lattice origin)
+ *   level     refinement level, 0 <= level <= TMF_MAX_LEVEL_P1 (P2 operators
+ *             further require level <= TMF_MAX_LEVEL_P2)
+ *   map       TMF_MAP_AFFINE or TMF_MAP_SHELL_RADIAL
+ * Errors: TMF_EINVAL for nv < 4, nt < 1, ids out of range, repeated ids in a
+ * tet, zero-volume tets, a face shared by more than two tets, non-finite
+ * coordinates, a bad level or map, or (SHELL_RADIAL) a tet not contained in
+ * one octant or touching the origin. */
+tmf_status tmf_mesh_create(const double *vertices, int64_t nv, const int64_t *tets, int64_t nt,
+                           int level, int map, tmf_mesh **out);
+void tmf_mesh_destroy(tmf_mesh *mesh);
+
+/* Sizes of the macro-local layout of space 1 (P1) or 2 (P2): n_local scalar
+ * slots per component (nt * C3(N)) and the number of distinct DoFs. */
+tmf_status tmf_mesh_layout(const tmf_mesh *mesh, int space, int64_t *n_local, int64_t *n_unique);
+
+/* Host-side description of every slot of the layout of `space`.  Each output
+ * may be NULL; non-NULL outputs are caller-allocated host arrays:
+ *   keys      n_local x 8 int64 canonical keys (pairs (vertex id, integer))
+ *   xyz       n_local x 3 doubles, physical position (after the map)
+ *   owner     n_local bytes, 1 on exactly one copy of each DoF
+ *   boundary  n_local bytes, 1 if the DoF is on the domain boundary */
+tmf_status tmf_mesh_dof_info(const tmf_mesh *mesh, int space, int64_t *keys, double *xyz,
+                             uint8_t *owner, uint8_t *boundary);
+
+/* Create an operator on `mesh` (the mesh must outlive the operator).
+ *   kind   TMF_P1_LAPLACE .. TMF_P2V_EPSILON
+ *   prec   TMF_F64 or TMF_F32: element type of coefficient, x and y; the
+ *          geometry constants are computed in FP64 on the host and rounded
+ *          once for TMF_F32
+ *   bc     TMF_BC_NONE or TMF_BC_DIRICHLET_ZERO
+ *   qbary, qw, nq   quadrature rule on the reference tet (host arrays: nq x 4
+ *          barycentric coordinates, nq weights summing to 1/6).  Required
+ *          (1 <= nq <= TMF_MAX_QUAD) for the blended shell map, which only the
+ *          epsilon operator supports; must be NULL/NULL/0 for affine meshes,
+ *          whose forms are integrated exactly.
+ * Allocates the operator's device tables on the current HIP device.
+ * Errors: TMF_EINVAL (bad enum, level above the space maximum, bad rule),
+ * TMF_EUNSUPPORTED (blended map with a scalar kind), TMF_ENOMEM, TMF_EDEVICE. */
+tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const double *qbary,
+                         const double *qw, int nq, tmf_op **out);
+void tmf_op_destroy(tmf_op *op);
+
+/* n_local per component, n_unique scalar DoFs per component, components (1 or 3),
+ * and whether the kind takes a coefficient field. */
+tmf_status tmf_op_info(const tmf_op *op, int64_t *n_local, int64_t *n_unique, int *ncomp,
+                       int *has_coeff);
+
+/* y = A(coeff) x (device pointers, element type per the op's precision).
+ * coeff: n_local values for the DIVKGRAD and EPSILON kinds, NULL otherwise.
+ * x, y: ncomp * n_local values; y must not alias x or coeff. */
+tmf_status tmf_apply(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream);
+
+/* Reverse-mode derivative of y = A(k) x for TMF_P1_DIVKGRAD (FP64 or FP32):
+ * given gy = dL/dy, writes gx = A(k)^T gy = A(k) gy (the operator, D A D
+ * included, is symmetric) and, if gk != NULL, gk_m = dL/dk_m = gy . (dA/dk_m) x
+ * for every coefficient DoF m, on every copy.  All pointers are device
+ * arrays of n_local values; gx and gk must not alias each other or any input.
+ * Other kinds return TMF_EUNSUPPORTED. */
+tmf_status tmf_apply_adjoint(tmf_op *op, const void *coeff, const void *x, const void *gy,
+                             void *gx, void *gk, tmf_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TETMF_H */

@@ -1,0 +1,671 @@
+// Host runtime and C ABI of the tetmf library.
+//
+// Mesh creation validates the macro mesh and derives, per macro-tet, the
+// boundary classification of its lattice points and the duplicate groups of
+// DoFs shared between macro-tets.  Operator creation computes the per-(macro,
+// micro-tet type) geometry constants in FP64 (the loop invariants of section
+// "Automatic Identification of Loop Invariants": translation invariance makes
+// every micro-tet of one type share its Jacobian) and uploads them with the
+// tile lists the element kernels walk.  Apply calls only validate and launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/tetmf.h"
+#include "tmf_internal.h"
+
+using namespace tmf;
+
+namespace {
+
+thread_local std::string g_err;
+
+tmf_status fail(tmf_status code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+tmf_status hip_fail(hipError_t e, const char *what) {
+  return fail(TMF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+using Key = std::array<int64_t, 8>;
+struct KeyHash {
+  size_t operator()(const Key &k) const {
+    uint64_t h = 0x9E3779B97F4A7C15ull;
+    for (int64_t v : k) {
+      h ^= static_cast<uint64_t>(v) + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+    }
+    return static_cast<size_t>(h);
+  }
+};
+
+// canonical key of lattice point (i,j,k) of a macro with vertex ids g
+Key point_key(const int64_t g[4], int i, int j, int k, int N) {
+  const int64_t a[4] = {N - i - j - k, i, j, k};
+  std::array<std::pair<int64_t, int64_t>, 4> p;
+  int n = 0;
+  for (int f = 0; f < 4; ++f)
+    if (a[f] > 0) p[n++] = {g[f], a[f]};
+  std::sort(p.begin(), p.begin() + n);
+  Key key;
+  for (int q = 0; q < 4; ++q) {
+    key[2 * q] = q < n ? p[q].first : -1;
+    key[2 * q + 1] = q < n ? p[q].second : 0;
+  }
+  return key;
+}
+
+template <typename T>
+struct DevBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  tmf_status upload(const void *src, size_t count) {
+    n = count;
+    if (count == 0) return TMF_OK;
+    if (hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T)) != hipSuccess) {
+      p = nullptr;
+      return fail(TMF_ENOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
+    }
+    hipError_t e = hipMemcpy(p, src, count * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    return TMF_OK;
+  }
+};
+
+void inv3(const double J[9], double Ji[9], double *det) {
+  Ji[0] = J[4] * J[8] - J[5] * J[7];
+  Ji[1] = J[2] * J[7] - J[1] * J[8];
+  Ji[2] = J[1] * J[5] - J[2] * J[4];
+  Ji[3] = J[5] * J[6] - J[3] * J[8];
+  Ji[4] = J[0] * J[8] - J[2] * J[6];
+  Ji[5] = J[2] * J[3] - J[0] * J[5];
+  Ji[6] = J[3] * J[7] - J[4] * J[6];
+  Ji[7] = J[1] * J[6] - J[0] * J[7];
+  Ji[8] = J[0] * J[4] - J[1] * J[3];
+  *det = J[0] * Ji[0] + J[1] * Ji[3] + J[2] * Ji[6];
+  for (int q = 0; q < 9; ++q) Ji[q] /= *det;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ mesh
+struct SpaceLayout {
+  bool built = false;
+  int N = 0;
+  int64_t L = 0, n_local = 0, n_unique = 0;
+  std::vector<int64_t> gptr, gidx;  // duplicate groups (size >= 2), members ascending
+  std::vector<uint8_t> owner;
+};
+
+struct tmf_mesh {
+  int level = 0, n = 1, map = 0;
+  int64_t nv = 0, nt = 0;
+  std::vector<double> V;
+  std::vector<int64_t> T;
+  std::vector<uint32_t> bnd;  // per macro: boundary bit per zero pattern
+  std::vector<double> sgn;    // per macro octant signs (shell map)
+  SpaceLayout sp[3];
+};
+
+static void build_layout(tmf_mesh *m, int space) {
+  SpaceLayout &S = m->sp[space];
+  if (S.built) return;
+  S.N = m->n * space;
+  S.L = c3(S.N);
+  S.n_local = m->nt * S.L;
+  std::unordered_map<Key, std::vector<int64_t>, KeyHash> groups;
+  const int N = S.N;
+  for (int64_t mac = 0; mac < m->nt; ++mac) {
+    const int64_t *g = &m->T[4 * mac];
+    for (int k = 0; k <= N; ++k)
+      for (int j = 0; j <= N - k; ++j)
+        for (int i = 0; i <= N - k - j; ++i) {
+          if (zero_pattern(i, j, k, N) == 0) continue;
+          groups[point_key(g, i, j, k, N)].push_back(mac * S.L + row_base(j, k, N) + i);
+        }
+  }
+  S.owner.assign(S.n_local, 1);
+  std::vector<std::vector<int64_t> *> list;
+  for (auto &kv : groups)
+    if (kv.second.size() > 1) list.push_back(&kv.second);
+  for (auto *v : list) std::sort(v->begin(), v->end());
+  std::sort(list.begin(), list.end(),
+            [](const std::vector<int64_t> *a, const std::vector<int64_t> *b) { return (*a)[0] < (*b)[0]; });
+  S.gptr.assign(1, 0);
+  S.gidx.clear();
+  int64_t dup = 0;
+  for (auto *v : list) {
+    for (size_t q = 0; q < v->size(); ++q) {
+      S.gidx.push_back((*v)[q]);
+      if (q > 0) S.owner[(*v)[q]] = 0;
+    }
+    dup += static_cast<int64_t>(v->size()) - 1;
+    S.gptr.push_back(static_cast<int64_t>(S.gidx.size()));
+  }
+  S.n_unique = S.n_local - dup;
+  S.built = true;
+}
+
+extern "C" {
+
+const char *tmf_version(void) { return "tetmf 0.1 (gfx950)"; }
+const char *tmf_last_error(void) { return g_err.c_str(); }
+const char *tmf_status_string(tmf_status s) {
+  switch (s) {
+    case TMF_OK: return "ok";
+    case TMF_EINVAL: return "invalid argument";
+    case TMF_ENOMEM: return "out of memory";
+    case TMF_EDEVICE: return "device error";
+    case TMF_EUNSUPPORTED: return "unsupported";
+    case TMF_ENOTCONV: return "not converged";
+    default: return "unknown status";
+  }
+}
+
+tmf_status tmf_mesh_create(const double *vertices, int64_t nv, const int64_t *tets, int64_t nt,
+                           int level, int map, tmf_mesh **out) {
+  if (!out) return fail(TMF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!vertices || !tets) return fail(TMF_EINVAL, "vertices or tets is NULL");
+  if (nv < 4 || nt < 1) return fail(TMF_EINVAL, "need nv >= 4 and nt >= 1 (got %lld, %lld)",
+                                    (long long)nv, (long long)nt);
+  if (level < 0 || level > TMF_MAX_LEVEL_P1)
+    return fail(TMF_EINVAL, "level %d outside [0, %d]", level, TMF_MAX_LEVEL_P1);
+  if (map != TMF_MAP_AFFINE && map != TMF_MAP_SHELL_RADIAL) return fail(TMF_EINVAL, "bad map %d", map);
+  for (int64_t q = 0; q < 3 * nv; ++q)
+    if (!std::isfinite(vertices[q])) return fail(TMF_EINVAL, "non-finite vertex coordinate");
+  double scale = 0;
+  for (int64_t q = 0; q < 3 * nv; ++q) scale = std::max(scale, std::fabs(vertices[q]));
+  if (scale == 0) return fail(TMF_EINVAL, "all vertices at the origin");
+  std::map<std::array<int64_t, 3>, int> faces;
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t *g = tets + 4 * t;
+    for (int a = 0; a < 4; ++a) {
+      if (g[a] < 0 || g[a] >= nv) return fail(TMF_EINVAL, "tet %lld: vertex id out of range", (long long)t);
+      for (int b = 0; b < a; ++b)
+        if (g[a] == g[b]) return fail(TMF_EINVAL, "tet %lld: repeated vertex id", (long long)t);
+    }
+    double J[9];
+    for (int d = 0; d < 3; ++d)
+      for (int c = 0; c < 3; ++c) J[3 * d + c] = vertices[3 * g[c + 1] + d] - vertices[3 * g[0] + d];
+    const double det = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                       J[2] * (J[3] * J[7] - J[4] * J[6]);
+    if (!(std::fabs(det) > 1e-12 * scale * scale * scale))
+      return fail(TMF_EINVAL, "tet %lld has (nearly) zero volume", (long long)t);
+    for (int f = 0; f < 4; ++f) {
+      std::array<int64_t, 3> key;
+      int q = 0;
+      for (int a = 0; a < 4; ++a)
+        if (a != f) key[q++] = g[a];
+      std::sort(key.begin(), key.end());
+      if (++faces[key] > 2) return fail(TMF_EINVAL, "a face is shared by more than two tets");
+    }
+  }
+  auto *m = new (std::nothrow) tmf_mesh;
+  if (!m) return fail(TMF_ENOMEM, "host allocation failed");
+  m->level = level;
+  m->n = 1 << level;
+  m->map = map;
+  m->nv = nv;
+  m->nt = nt;
+  m->V.assign(vertices, vertices + 3 * nv);
+  m->T.assign(tets, tets + 4 * nt);
+  m->sgn.assign(3 * nt, 1.0);
+  if (map == TMF_MAP_SHELL_RADIAL) {
+    for (int64_t t = 0; t < nt; ++t) {
+      const int64_t *g = tets + 4 * t;
+      for (int d = 0; d < 3; ++d) {
+        double c = 0;
+        for (int a = 0; a < 4; ++a) c += vertices[3 * g[a] + d];
+        const double s = c >= 0 ? 1.0 : -1.0;
+        for (int a = 0; a < 4; ++a)
+          if (s * vertices[3 * g[a] + d] < -1e-14 * scale) {
+            delete m;
+            return fail(TMF_EINVAL, "tet %lld is not inside one coordinate octant", (long long)t);
+          }
+        m->sgn[3 * t + d] = s;
+      }
+      for (int a = 0; a < 4; ++a) {
+        const double *p = vertices + 3 * g[a];
+        if (std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) < 1e-12 * scale) {
+          delete m;
+          return fail(TMF_EINVAL, "tet %lld touches the origin", (long long)t);
+        }
+      }
+    }
+  }
+  // domain boundary: faces of a single tet, with their edges and vertices
+  std::map<std::vector<int64_t>, bool> bsimp;
+  for (auto &kv : faces) {
+    if (kv.second != 1) continue;
+    const auto &f = kv.first;
+    bsimp[{f[0], f[1], f[2]}] = true;
+    bsimp[{f[0], f[1]}] = true;
+    bsimp[{f[0], f[2]}] = true;
+    bsimp[{f[1], f[2]}] = true;
+    bsimp[{f[0]}] = true;
+    bsimp[{f[1]}] = true;
+    bsimp[{f[2]}] = true;
+  }
+  m->bnd.assign(nt, 0u);
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t *g = tets + 4 * t;
+    uint32_t mask = 0;
+    for (int z = 1; z < 15; ++z) {
+      std::vector<int64_t> s;
+      for (int f = 0; f < 4; ++f)
+        if (!((z >> f) & 1)) s.push_back(g[f]);
+      std::sort(s.begin(), s.end());
+      if (bsimp.count(s)) mask |= 1u << z;
+    }
+    m->bnd[t] = mask;
+  }
+  *out = m;
+  return TMF_OK;
+}
+
+void tmf_mesh_destroy(tmf_mesh *mesh) { delete mesh; }
+
+tmf_status tmf_mesh_layout(const tmf_mesh *mesh, int space, int64_t *n_local, int64_t *n_unique) {
+  if (!mesh) return fail(TMF_EINVAL, "mesh is NULL");
+  if (space != 1 && space != 2) return fail(TMF_EINVAL, "space must be 1 or 2");
+  if (space == 2 && mesh->level > TMF_MAX_LEVEL_P2)
+    return fail(TMF_EINVAL, "P2 space supports level <= %d", TMF_MAX_LEVEL_P2);
+  build_layout(const_cast<tmf_mesh *>(mesh), space);
+  if (n_local) *n_local = mesh->sp[space].n_local;
+  if (n_unique) *n_unique = mesh->sp[space].n_unique;
+  return TMF_OK;
+}
+
+tmf_status tmf_mesh_dof_info(const tmf_mesh *mesh, int space, int64_t *keys, double *xyz, uint8_t *owner,
+                             uint8_t *boundary) {
+  tmf_status st = tmf_mesh_layout(mesh, space, nullptr, nullptr);
+  if (st != TMF_OK) return st;
+  const SpaceLayout &S = mesh->sp[space];
+  const int N = S.N;
+  for (int64_t mac = 0; mac < mesh->nt; ++mac) {
+    const int64_t *g = &mesh->T[4 * mac];
+    const uint32_t bm = mesh->bnd[mac];
+    for (int k = 0; k <= N; ++k)
+      for (int j = 0; j <= N - k; ++j)
+        for (int i = 0; i <= N - k - j; ++i) {
+          const int64_t slot = mac * S.L + row_base(j, k, N) + i;
+          if (keys) {
+            Key key = point_key(g, i, j, k, N);
+            std::memcpy(keys + 8 * slot, key.data(), sizeof(Key));
+          }
+          if (xyz) {
+            const double a[4] = {double(N - i - j - k), double(i), double(j), double(k)};
+            double p[3] = {0, 0, 0};
+            for (int f = 0; f < 4; ++f)
+              for (int d = 0; d < 3; ++d) p[d] += a[f] * mesh->V[3 * g[f] + d];
+            for (int d = 0; d < 3; ++d) p[d] /= N;
+            if (mesh->map == TMF_MAP_SHELL_RADIAL) {
+              const double l1 = std::fabs(p[0]) + std::fabs(p[1]) + std::fabs(p[2]);
+              const double l2 = std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+              for (int d = 0; d < 3; ++d) p[d] *= l1 / l2;
+            }
+            for (int d = 0; d < 3; ++d) xyz[3 * slot + d] = p[d];
+          }
+          if (owner) owner[slot] = S.owner[slot];
+          if (boundary) boundary[slot] = (bm >> zero_pattern(i, j, k, N)) & 1u;
+        }
+  }
+  return TMF_OK;
+}
+
+}  // extern "C"
+
+// -------------------------------------------------------------- operator
+struct tmf_op {
+  const tmf_mesh *mesh = nullptr;
+  int kind = 0, prec = 0, bc = 0, space = 1, ncomp = 1, N = 1, nq = 0;
+  int64_t L = 0, n_local = 0, n_unique = 0;
+  int tile_cfg = 0;
+  DevBuf<uint8_t> geo, w15, mgeo, qtab;
+  DevBuf<uint32_t> bnd;
+  DevBuf<int4> tiles[kNumTileCfg];
+  int ntiles[kNumTileCfg] = {0};
+  DevBuf<int64_t> gptr, gidx;
+  int64_t ngroups = 0;
+  DevBuf<uint8_t> owner;
+};
+
+namespace {
+
+bool has_coeff(int kind) { return kind == TMF_P1_DIVKGRAD || kind == TMF_P2_DIVKGRAD || kind == TMF_P2V_EPSILON; }
+
+template <typename T>
+void fill_geometry(const tmf_mesh *m, std::vector<TypeGeo<T>> &geo, std::vector<T> &w15,
+                   std::vector<MacroGeo<T>> &mg) {
+  geo.assign(6 * m->nt, TypeGeo<T>{});
+  w15.assign(15 * m->nt, T(0));
+  mg.assign(m->nt, MacroGeo<T>{});
+  for (int64_t mac = 0; mac < m->nt; ++mac) {
+    const int64_t *g = &m->T[4 * mac];
+    double JM[9];
+    for (int d = 0; d < 3; ++d)
+      for (int c = 0; c < 3; ++c) JM[3 * d + c] = m->V[3 * g[c + 1] + d] - m->V[3 * g[0] + d];
+    for (int d = 0; d < 3; ++d) {
+      mg[mac].v0[d] = T(m->V[3 * g[0] + d]);
+      mg[mac].s[d] = T(m->sgn[3 * mac + d]);
+    }
+    for (int q = 0; q < 9; ++q) mg[mac].JM[q] = T(JM[q]);
+    double w[15] = {0};
+    for (int t = 0; t < 6; ++t) {
+      double E[9], J[9], Ji[9], det;
+      for (int d = 0; d < 3; ++d)
+        for (int c = 0; c < 3; ++c) E[3 * d + c] = kOff[t][c + 1][d] - kOff[t][0][d];
+      for (int d = 0; d < 3; ++d)
+        for (int c = 0; c < 3; ++c) {
+          double s = 0;
+          for (int q = 0; q < 3; ++q) s += JM[3 * d + q] * E[3 * q + c];
+          J[3 * d + c] = s / m->n;
+        }
+      inv3(J, Ji, &det);
+      const double vol = std::fabs(det) / 6.0;
+      double gr[4][3];
+      for (int d = 0; d < 3; ++d) {
+        gr[1][d] = Ji[0 * 3 + d];
+        gr[2][d] = Ji[1 * 3 + d];
+        gr[3][d] = Ji[2 * 3 + d];
+        gr[0][d] = -(gr[1][d] + gr[2][d] + gr[3][d]);
+      }
+      TypeGeo<T> &tg = geo[6 * mac + t];
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+          const double v = vol * (gr[a][0] * gr[b][0] + gr[a][1] * gr[b][1] + gr[a][2] * gr[b][2]);
+          tg.Gp[4 * a + b] = T(v);
+        }
+      for (int a = 0; a < 4; ++a)
+        for (int d = 0; d < 3; ++d) tg.grad[3 * a + d] = T(gr[a][d]);
+      tg.vol = T(vol);
+      for (int q = 0; q < 9; ++q) tg.JT[q] = T(J[q]);
+      for (int a = 0; a < 4; ++a)
+        for (int c = 0; c < 4; ++c)
+          w[vslot(t, a, c)] += vol * (gr[a][0] * gr[c][0] + gr[a][1] * gr[c][1] + gr[a][2] * gr[c][2]);
+    }
+    for (int q = 0; q < 15; ++q) w15[15 * mac + q] = T(w[q]);
+  }
+}
+
+template <typename T>
+void fill_qtab(const double *qb, const double *qw, int nq, std::vector<T> &out) {
+  out.assign(static_cast<size_t>(nq) * kQStride, T(0));
+  for (int q = 0; q < nq; ++q) {
+    T *Q = out.data() + static_cast<size_t>(q) * kQStride;
+    const double *l = qb + 4 * q;
+    Q[0] = T(qw[q]);
+    for (int a = 0; a < 4; ++a) Q[1 + a] = T(l[a]);
+    double phi[10], dphi[10][4] = {{0}};
+    for (int a = 0; a < 4; ++a) {
+      phi[a] = l[a] * (2 * l[a] - 1);
+      dphi[a][a] = 4 * l[a] - 1;
+    }
+    for (int e = 0; e < 6; ++e) {
+      const int a = kEdge[e][0], b = kEdge[e][1];
+      phi[4 + e] = 4 * l[a] * l[b];
+      dphi[4 + e][a] = 4 * l[b];
+      dphi[4 + e][b] = 4 * l[a];
+    }
+    for (int i = 0; i < 10; ++i) {
+      Q[5 + i] = T(phi[i]);
+      for (int r = 0; r < 3; ++r) Q[15 + 3 * i + r] = T(dphi[i][r + 1] - dphi[i][0]);
+    }
+  }
+}
+
+template <typename T>
+tmf_status upload_vec(DevBuf<uint8_t> &buf, const std::vector<T> &v) {
+  return buf.upload(v.data(), v.size() * sizeof(T));
+}
+
+}  // namespace
+
+extern "C" {
+
+tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const double *qbary,
+                         const double *qw, int nq, tmf_op **out) {
+  if (!out) return fail(TMF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!mesh) return fail(TMF_EINVAL, "mesh is NULL");
+  if (kind < TMF_P1_LAPLACE || kind > TMF_P2V_EPSILON) return fail(TMF_EINVAL, "bad operator kind %d", kind);
+  if (prec != TMF_F64 && prec != TMF_F32) return fail(TMF_EINVAL, "bad precision %d", prec);
+  if (bc != TMF_BC_NONE && bc != TMF_BC_DIRICHLET_ZERO) return fail(TMF_EINVAL, "bad boundary condition %d", bc);
+  const int space = kind <= TMF_P1_DIVKGRAD ? 1 : 2;
+  if (space == 2 && mesh->level > TMF_MAX_LEVEL_P2)
+    return fail(TMF_EINVAL, "P2 operators support level <= %d", TMF_MAX_LEVEL_P2);
+  if (mesh->map == TMF_MAP_SHELL_RADIAL) {
+    if (kind != TMF_P2V_EPSILON)
+      return fail(TMF_EUNSUPPORTED, "the blended shell map is supported for the epsilon operator only");
+    if (!qbary || !qw || nq < 1 || nq > TMF_MAX_QUAD)
+      return fail(TMF_EINVAL, "the blended map needs a quadrature rule with 1..%d points", TMF_MAX_QUAD);
+    double wsum = 0;
+    for (int q = 0; q < nq; ++q) {
+      double s = 0;
+      for (int a = 0; a < 4; ++a) {
+        if (!std::isfinite(qbary[4 * q + a])) return fail(TMF_EINVAL, "non-finite quadrature point");
+        s += qbary[4 * q + a];
+      }
+      if (std::fabs(s - 1.0) > 1e-12) return fail(TMF_EINVAL, "quadrature point %d: barycentric sum != 1", q);
+      if (!std::isfinite(qw[q])) return fail(TMF_EINVAL, "non-finite quadrature weight");
+      wsum += qw[q];
+    }
+    if (std::fabs(wsum - 1.0 / 6.0) > 1e-12) return fail(TMF_EINVAL, "quadrature weights must sum to 1/6");
+  } else if (qbary || qw || nq != 0) {
+    return fail(TMF_EINVAL, "affine operators are integrated exactly: pass no quadrature rule");
+  }
+  tmf_mesh *mm = const_cast<tmf_mesh *>(mesh);
+  build_layout(mm, space);
+  const SpaceLayout &S = mesh->sp[space];
+
+  auto *op = new (std::nothrow) tmf_op;
+  if (!op) return fail(TMF_ENOMEM, "host allocation failed");
+  op->mesh = mesh;
+  op->kind = kind;
+  op->prec = prec;
+  op->bc = bc;
+  op->space = space;
+  op->ncomp = kind == TMF_P2V_EPSILON ? 3 : 1;
+  op->N = S.N;
+  op->L = S.L;
+  op->n_local = S.n_local;
+  op->n_unique = S.n_unique;
+  op->nq = mesh->map == TMF_MAP_SHELL_RADIAL ? nq : 0;
+  tmf_status st = TMF_OK;
+  if (prec == TMF_F64) {
+    std::vector<TypeGeo<double>> g;
+    std::vector<double> w;
+    std::vector<MacroGeo<double>> mg;
+    fill_geometry(mesh, g, w, mg);
+    st = upload_vec(op->geo, g);
+    if (st == TMF_OK) st = upload_vec(op->w15, w);
+    if (st == TMF_OK) st = upload_vec(op->mgeo, mg);
+    if (st == TMF_OK && op->nq) {
+      std::vector<double> q;
+      fill_qtab(qbary, qw, nq, q);
+      st = upload_vec(op->qtab, q);
+    }
+  } else {
+    std::vector<TypeGeo<float>> g;
+    std::vector<float> w;
+    std::vector<MacroGeo<float>> mg;
+    fill_geometry(mesh, g, w, mg);
+    st = upload_vec(op->geo, g);
+    if (st == TMF_OK) st = upload_vec(op->w15, w);
+    if (st == TMF_OK) st = upload_vec(op->mgeo, mg);
+    if (st == TMF_OK && op->nq) {
+      std::vector<float> q;
+      fill_qtab(qbary, qw, nq, q);
+      st = upload_vec(op->qtab, q);
+    }
+  }
+  if (st == TMF_OK) st = op->bnd.upload(mesh->bnd.data(), mesh->bnd.size());
+  if (st == TMF_OK && space == 2) {
+    const int n = mesh->n;
+    for (int cfg = 0; cfg < kNumTileCfg && st == TMF_OK; ++cfg) {
+      const int TX = kTileCfg[cfg][0], TY = kTileCfg[cfg][1], TZ = kTileCfg[cfg][2];
+      std::vector<int4> tl;
+      for (int64_t mac = 0; mac < mesh->nt; ++mac)
+        for (int bz = 0; bz < n; bz += TZ)
+          for (int by = 0; by < n - bz; by += TY)
+            for (int bx = 0; bx < n - bz - by; bx += TX) tl.push_back(make_int4(int(mac), bx, by, bz));
+      op->ntiles[cfg] = static_cast<int>(tl.size());
+      st = op->tiles[cfg].upload(tl.data(), tl.size());
+    }
+  }
+  if (st == TMF_OK) {
+    op->ngroups = static_cast<int64_t>(S.gptr.size()) - 1;
+    st = op->gptr.upload(S.gptr.data(), S.gptr.size());
+    if (st == TMF_OK) st = op->gidx.upload(S.gidx.data(), S.gidx.size());
+    if (st == TMF_OK) st = op->owner.upload(S.owner.data(), S.owner.size());
+  }
+  if (st != TMF_OK) {
+    delete op;
+    return st;
+  }
+  *out = op;
+  return TMF_OK;
+}
+
+void tmf_op_destroy(tmf_op *op) { delete op; }
+
+tmf_status tmf_op_info(const tmf_op *op, int64_t *n_local, int64_t *n_unique, int *ncomp, int *has_c) {
+  if (!op) return fail(TMF_EINVAL, "op is NULL");
+  if (n_local) *n_local = op->n_local;
+  if (n_unique) *n_unique = op->n_unique;
+  if (ncomp) *ncomp = op->ncomp;
+  if (has_c) *has_c = has_coeff(op->kind) ? 1 : 0;
+  return TMF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+LatticeArgs<T> lattice_args(const tmf_op *op) {
+  LatticeArgs<T> L;
+  L.n = op->mesh->n;
+  L.N = op->N;
+  L.nt = static_cast<int>(op->mesh->nt);
+  L.L = static_cast<int>(op->L);
+  L.dirichlet = op->bc == TMF_BC_DIRICHLET_ZERO;
+  L.bnd = op->bnd.p;
+  L.geo = reinterpret_cast<const TypeGeo<T> *>(op->geo.p);
+  return L;
+}
+
+GroupArgs group_args(const tmf_op *op) {
+  GroupArgs g;
+  g.ptr = op->gptr.p;
+  g.idx = op->gidx.p;
+  g.ngroups = op->ngroups;
+  g.n_local = op->n_local;
+  g.ncomp = op->ncomp;
+  return g;
+}
+
+template <typename T>
+hipError_t apply_t(tmf_op *op, const void *coeff, const void *x, void *y, hipStream_t s) {
+  hipError_t e;
+  T *yy = static_cast<T *>(y);
+  if (op->space == 1) {
+    P1Args<T> a;
+    a.lat = lattice_args<T>(op);
+    a.w15 = reinterpret_cast<const T *>(op->w15.p);
+    a.k = static_cast<const T *>(coeff);
+    a.x = static_cast<const T *>(x);
+    a.y = yy;
+    e = launch_p1_apply<T>(a, op->kind, s);
+  } else {
+    e = launch_fill<T>(yy, op->ncomp * op->n_local, T(0), s);
+    if (e != hipSuccess) return e;
+    TileArgs<T> a;
+    a.lat = lattice_args<T>(op);
+    a.tiles = op->tiles[op->tile_cfg].p;
+    a.ntiles = op->ntiles[op->tile_cfg];
+    a.n_local = op->n_local;
+    a.mgeo = reinterpret_cast<const MacroGeo<T> *>(op->mgeo.p);
+    a.qtab = reinterpret_cast<const T *>(op->qtab.p);
+    a.nq = op->nq;
+    a.k = static_cast<const T *>(coeff);
+    a.x = static_cast<const T *>(x);
+    a.y = yy;
+    e = launch_tile_apply<T>(a, op->kind, op->mesh->map, op->tile_cfg, s);
+  }
+  if (e != hipSuccess) return e;
+  return launch_interface_sum<T>(group_args(op), yy, s);
+}
+
+template <typename T>
+hipError_t adjoint_t(tmf_op *op, const void *coeff, const void *x, const void *gy, void *gx, void *gk,
+                     hipStream_t s) {
+  P1AdjArgs<T> a;
+  a.lat = lattice_args<T>(op);
+  a.k = static_cast<const T *>(coeff);
+  a.x = static_cast<const T *>(x);
+  a.gy = static_cast<const T *>(gy);
+  a.gx = static_cast<T *>(gx);
+  a.gk = static_cast<T *>(gk);
+  hipError_t e = launch_p1_adjoint<T>(a, s);
+  if (e != hipSuccess) return e;
+  GroupArgs g = group_args(op);
+  e = launch_interface_sum<T>(g, a.gx, s);
+  if (e != hipSuccess || !gk) return e;
+  return launch_interface_sum<T>(g, a.gk, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+tmf_status tmf_apply(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream) {
+  if (!op) return fail(TMF_EINVAL, "op is NULL");
+  if (!x || !y) return fail(TMF_EINVAL, "x or y is NULL");
+  if (has_coeff(op->kind) != (coeff != nullptr))
+    return fail(TMF_EINVAL, has_coeff(op->kind) ? "this operator needs a coefficient field"
+                                                : "this operator takes no coefficient field");
+  if (y == x || (coeff && y == coeff)) return fail(TMF_EINVAL, "y must not alias x or the coefficient");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = op->prec == TMF_F64 ? apply_t<double>(op, coeff, x, y, s) : apply_t<float>(op, coeff, x, y, s);
+  if (e != hipSuccess) return hip_fail(e, "apply launch");
+  return TMF_OK;
+}
+
+tmf_status tmf_apply_adjoint(tmf_op *op, const void *coeff, const void *x, const void *gy, void *gx, void *gk,
+                             tmf_stream stream) {
+  if (!op) return fail(TMF_EINVAL, "op is NULL");
+  if (op->kind != TMF_P1_DIVKGRAD)
+    return fail(TMF_EUNSUPPORTED, "the fused adjoint is implemented for TMF_P1_DIVKGRAD");
+  if (!coeff || !x || !gy || !gx) return fail(TMF_EINVAL, "coeff, x, gy and gx are required");
+  const void *ins[3] = {coeff, x, gy};
+  for (const void *p : ins)
+    if (p == gx || (gk && p == gk)) return fail(TMF_EINVAL, "outputs must not alias inputs");
+  if (gk && gk == gx) return fail(TMF_EINVAL, "gx and gk must differ");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = op->prec == TMF_F64 ? adjoint_t<double>(op, coeff, x, gy, gx, gk, s)
+                                     : adjoint_t<float>(op, coeff, x, gy, gx, gk, s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+  return TMF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,468 @@
+// P2 and vector-P2 operators: element-centric kernels over LDS-staged tiles.
+//
+// A workgroup owns a box of TX x TY x TZ micro-cubes of one macro (the
+// spatial blocking of section "Cubes Loop Strategy": all micro-tets of a
+// cube, and of neighbouring cubes, reuse DoFs already staged on chip).  It
+//   1. stages the (2TX+1)(2TY+1)(2TZ+1) P2 lattice points of the box (x, the
+//      coefficient, Dirichlet mask applied to x) from HBM into LDS,
+//   2. applies the fused local operator to every micro-tet of the box -- one
+//      lane per micro-tet, one type per wavefront -- and accumulates the 10
+//      (or 30) local results into an LDS copy of y,
+//   3. writes y: points touched only by this box are stored directly; points
+//      on the box faces shared with neighbouring boxes are added into y
+//      (zero-filled beforehand) with hardware FP atomics.
+// The local operator is never formed (remark on fused local quadrature after
+// algorithm "LocalApply"): for affine elements the gradient of a P2 field is
+// a P1 field, grad u = sum_a lambda_a g_a, and every integral becomes a
+// product with exact weights int k lambda_a lambda_e; see p2_elem.
+#include "tmf_internal.h"
+
+namespace tmf {
+
+namespace {
+
+__device__ inline bool is_bnd(uint32_t bnd, int i, int j, int k, int N) {
+  return (bnd >> zero_pattern(i, j, k, N)) & 1u;
+}
+
+// Exact weights W_ce = (1/|T|) int_T k lambda_c lambda_e for k nodal P2.
+// k in Bernstein form: k = sum_b kappa_b B_b, B_aa = lambda_a^2,
+// B_ab = 2 lambda_a lambda_b, kappa_aa = k_a, kappa_ab = 2 k_ab - (k_a + k_b)/2.
+// With int lambda^g = 6|T| g!/(|g|+3)!:  W_ce = (kappa_ce + S1_c + S1_e + S0)/420
+// (c != e), W_cc = (S2_c + 3 S1_c + 2 S0)/420, S0 = sum kappa, S1_c = sum_b
+// kappa_b b_c, S2_c = sum_b kappa_b b_c^2.
+template <typename T>
+__device__ inline void weights_p2(const T kv[10], T W[4][4]) {
+  T kap[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) kap[a][a] = kv[a];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int a = kEdge[e][0], b = kEdge[e][1];
+    const T v = T(2) * kv[4 + e] - T(0.5) * (kv[a] + kv[b]);
+    kap[a][b] = v;
+    kap[b][a] = v;
+  }
+  T S0 = T(0), S1[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    T off = T(0);
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (b != c) off += kap[c][b];
+    S1[c] = T(2) * kap[c][c] + off;
+    S0 += kap[c][c];
+  }
+#pragma unroll
+  for (int e = 0; e < 6; ++e) S0 += kap[kEdge[e][0]][kEdge[e][1]];
+  const T s = T(1) / T(420);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    W[c][c] = (S1[c] + T(2) * kap[c][c] + T(3) * S1[c] + T(2) * S0) * s;
+#pragma unroll
+    for (int e = c + 1; e < 4; ++e) {
+      const T v = (kap[c][e] + S1[c] + S1[e] + S0) * s;
+      W[c][e] = v;
+      W[e][c] = v;
+    }
+  }
+}
+
+// Gradient coefficients of a P2 field on an affine tet in the barycentric
+// gradient basis: grad u = sum_c lambda_c g_c with g_c = sum_a s[c][a] grad(lambda_a),
+// s[c][c] = 3 u_c, s[c][a] = 4 u_ca - u_a.  Returned shifted by s[c][0]
+// (sum_a grad(lambda_a) = 0), as sp[c][a-1] for a = 1..3.
+template <typename T>
+__device__ inline void grad_coeffs(const T u[10], T sp[4][3]) {
+  T s[4][4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) s[c][c] = T(3) * u[c];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int a = kEdge[e][0], b = kEdge[e][1];
+    s[a][b] = T(4) * u[4 + e] - u[b];
+    s[b][a] = T(4) * u[4 + e] - u[a];
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int a = 1; a < 4; ++a) sp[c][a - 1] = s[c][a] - s[c][0];
+}
+
+// Fused local apply of int k grad u . grad phi_j on one affine tet.
+//   h[c][d] = g_c . |T| grad(lambda_d)          (16 values, Gp = |T| G)
+//   sigma[e][d] = sum_c W_ce h[c][d]
+//   y_vertex b = 4 sigma[b][b] - sum_e sigma[e][b]
+//   y_edge bc  = 4 (sigma[c][b] + sigma[b][c])
+// (from grad phi_b = (4 lambda_b - 1) grad lambda_b and
+//  grad phi_bc = 4 (lambda_c grad lambda_b + lambda_b grad lambda_c)).
+template <typename T, bool HASK>
+__device__ inline void p2_elem(const T u[10], const T kv[10], const T *__restrict__ Gp, T y[10]) {
+  T sp[4][3];
+  grad_coeffs(u, sp);
+  T h[4][4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int d = 1; d < 4; ++d)
+      h[c][d] = sp[c][0] * Gp[4 * 1 + d] + sp[c][1] * Gp[4 * 2 + d] + sp[c][2] * Gp[4 * 3 + d];
+    h[c][0] = -(h[c][1] + h[c][2] + h[c][3]);
+  }
+  T sig[4][4];
+  if (HASK) {
+    T W[4][4];
+    weights_p2(kv, W);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+        sig[e][d] = W[0][e] * h[0][d] + W[1][e] * h[1][d] + W[2][e] * h[2][d] + W[3][e] * h[3][d];
+  } else {
+    // W = (1 + delta)/20
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const T H = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sig[e][d] = (H + h[e][d]) * T(0.05);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+    y[b] = T(4) * sig[b][b] - (sig[0][b] + sig[1][b] + sig[2][b] + sig[3][b]);
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int b = kEdge[e][0], c = kEdge[e][1];
+    y[4 + e] = T(4) * (sig[c][b] + sig[b][c]);
+  }
+}
+
+// Fused local apply of int 2 mu eps(u):eps(v) on one affine tet.
+//   component gradients: grad u_c = sum_a lambda_a g^c_a
+//   strain at vertex a: E_a = sym(G_a), row c of G_a = g^c_a
+//   sigma_e = sum_a W_ae E_a   (W from mu as above)
+//   y_vertex b = 2|T| (4 sigma_b - sum_e sigma_e) grad lambda_b
+//   y_edge bc  = 8|T| (sigma_c grad lambda_b + sigma_b grad lambda_c)
+template <typename T>
+__device__ inline void eps_elem(const T u[3][10], const T mu[10], const T *__restrict__ grad, T vol,
+                                T y[3][10]) {
+  // g[c][a][r]
+  T E[4][6];  // symmetric strain per vertex: xx, yy, zz, xy, xz, yz
+  {
+    T g[3][4][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T sp[4][3];
+      grad_coeffs(u[c], sp);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+          g[c][a][r] = sp[a][0] * grad[3 * 1 + r] + sp[a][1] * grad[3 * 2 + r] + sp[a][2] * grad[3 * 3 + r];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      E[a][0] = g[0][a][0];
+      E[a][1] = g[1][a][1];
+      E[a][2] = g[2][a][2];
+      E[a][3] = T(0.5) * (g[0][a][1] + g[1][a][0]);
+      E[a][4] = T(0.5) * (g[0][a][2] + g[2][a][0]);
+      E[a][5] = T(0.5) * (g[1][a][2] + g[2][a][1]);
+    }
+  }
+  T W[4][4];
+  weights_p2(mu, W);
+  T sig[4][6], tot[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) tot[q] = T(0);
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      sig[e][q] = W[0][e] * E[0][q] + W[1][e] * E[1][q] + W[2][e] * E[2][q] + W[3][e] * E[3][q];
+      tot[q] += sig[e][q];
+    }
+  auto matvec = [](const T S[6], const T *v, T out[3]) {
+    out[0] = S[0] * v[0] + S[3] * v[1] + S[4] * v[2];
+    out[1] = S[3] * v[0] + S[1] * v[1] + S[5] * v[2];
+    out[2] = S[4] * v[0] + S[5] * v[1] + S[2] * v[2];
+  };
+  const T fv = T(2) * vol, fe = T(8) * vol;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    T S[6], o[3];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) S[q] = fv * (T(4) * sig[b][q] - tot[q]);
+    matvec(S, grad + 3 * b, o);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) y[c][b] = o[c];
+  }
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int b = kEdge[e][0], c2 = kEdge[e][1];
+    T o1[3], o2[3];
+    matvec(sig[c2], grad + 3 * b, o1);
+    matvec(sig[b], grad + 3 * c2, o2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) y[c][4 + e] = fe * (o1[c] + o2[c]);
+  }
+}
+
+// Epsilon operator on a curved element of the radially blended map
+// x = Phi(xi) = xi (s.xi)/|xi|, integrated with the given rule:
+//   xi_q = P0 + JT xhat_q, J = DPhi(xi_q) JT,
+//   grad u_c = (ref-grad u_c) J^-1,  sigma = 2 mu_q w_q |det J| sym(grad u),
+//   y_(i,d) += sum_r (sigma J^-T)_(d r) ref-grad_r phi_i(xhat_q).
+template <typename T>
+__device__ inline void eps_blended_elem(const T u[3][10], const T mu[10], const T P0[3],
+                                        const T *__restrict__ JT, const T s[3],
+                                        const T *__restrict__ qtab, int nq, T y[3][10]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < 10; ++i) y[c][i] = T(0);
+  for (int q = 0; q < nq; ++q) {
+    const T *Q = qtab + q * kQStride;  // w, bary[4], phi[10], refgrad[10][3]
+    const T xh[3] = {Q[2], Q[3], Q[4]};
+    T xi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xi[d] = P0[d] + JT[3 * d + 0] * xh[0] + JT[3 * d + 1] * xh[1] + JT[3 * d + 2] * xh[2];
+    const T rho = s[0] * xi[0] + s[1] * xi[1] + s[2] * xi[2];
+    const T n2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+    const T inv = T(1) / sqrt(n2);
+    const T a0 = rho * inv;
+    const T c3i = rho * inv * inv * inv;
+    T D[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) D[r][cc] = xi[r] * (s[cc] * inv - c3i * xi[cc]) + (r == cc ? a0 : T(0));
+    T J[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) J[r][cc] = D[r][0] * JT[0 + cc] + D[r][1] * JT[3 + cc] + D[r][2] * JT[6 + cc];
+    T Ji[3][3];
+    Ji[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    Ji[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    Ji[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    Ji[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    Ji[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    Ji[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    Ji[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    Ji[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    Ji[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const T det = J[0][0] * Ji[0][0] + J[0][1] * Ji[1][0] + J[0][2] * Ji[2][0];
+    const T idet = T(1) / det;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) Ji[r][cc] *= idet;
+    const T *RG = Q + 15;
+    T gr[3][3];  // reference gradient of each component
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        T acc = T(0);
+#pragma unroll
+        for (int i = 0; i < 10; ++i) acc += u[c][i] * RG[3 * i + r];
+        gr[c][r] = acc;
+      }
+    T gu[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) gu[c][d] = gr[c][0] * Ji[0][d] + gr[c][1] * Ji[1][d] + gr[c][2] * Ji[2][d];
+    T muq = T(0);
+#pragma unroll
+    for (int i = 0; i < 10; ++i) muq += mu[i] * Q[5 + i];
+    const T f = T(2) * muq * Q[0] * fabs(det);
+    T sg[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int e = 0; e < 3; ++e) sg[d][e] = f * T(0.5) * (gu[d][e] + gu[e][d]);
+    T S[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) S[d][r] = sg[d][0] * Ji[r][0] + sg[d][1] * Ji[r][1] + sg[d][2] * Ji[r][2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int i = 0; i < 10; ++i) y[d][i] += S[d][0] * RG[3 * i + 0] + S[d][1] * RG[3 * i + 1] + S[d][2] * RG[3 * i + 2];
+  }
+}
+
+template <typename T, int KIND, int MAP, int TX, int TY, int TZ>
+struct TileCfg {
+  static constexpr int RX = 2 * TX + 1, RY = 2 * TY + 1, RZ = 2 * TZ + 1;
+  static constexpr int R = RX * RY * RZ;
+  static constexpr int C = TX * TY * TZ;
+  static constexpr int NC = KIND == P2V_EPSILON ? 3 : 1;
+  static constexpr bool HASK = KIND != P2_LAPLACE;
+  static constexpr int NTH = (6 * C) < 768 ? 6 * C : 768;
+  static_assert(C % 64 == 0, "one micro-tet type per wavefront needs 64 | cubes per tile");
+};
+
+template <typename T, int KIND, int MAP, int TX, int TY, int TZ>
+__global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_tile(TileArgs<T> a) {
+  using Cfg = TileCfg<T, KIND, MAP, TX, TY, TZ>;
+  constexpr int RX = Cfg::RX, RY = Cfg::RY, R = Cfg::R, C = Cfg::C, NC = Cfg::NC, NTH = Cfg::NTH;
+  constexpr bool HASK = Cfg::HASK;
+  __shared__ T sx[NC][R];
+  __shared__ T sy[NC][R];
+  __shared__ T sk[HASK ? R : 1];
+  __shared__ int snoff[6][10];
+
+  const LatticeArgs<T> &L = a.lat;
+  const int4 tile = a.tiles[blockIdx.x];
+  const int m = tile.x;
+  const int bx0 = tile.y, by0 = tile.z, bz0 = tile.w;
+  const int N = L.N, n = L.n;
+  const uint32_t bnd = L.bnd[m];
+  const int64_t base = static_cast<int64_t>(m) * L.L;
+  const int tid = threadIdx.x;
+
+  if (tid < 60) {
+    const int t = tid / 10, v = tid % 10;
+    int o[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      o[d] = v < 4 ? 2 * kOff[t][v][d] : kOff[t][kEdge[v - 4][0]][d] + kOff[t][kEdge[v - 4][1]][d];
+    snoff[t][v] = o[0] + RX * (o[1] + RY * o[2]);
+  }
+  // 1. stage x (masked) and the coefficient
+  for (int r = tid; r < R; r += NTH) {
+    const int rx = r % RX, ry = (r / RX) % RY, rz = r / (RX * RY);
+    const int qi = 2 * bx0 + rx, qj = 2 * by0 + ry, qk = 2 * bz0 + rz;
+    T xv[NC], kv = T(0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) xv[c] = T(0);
+    if (qi + qj + qk <= N) {
+      const int64_t gi = base + row_base(qj, qk, N) + qi;
+      const bool masked = L.dirichlet && is_bnd(bnd, qi, qj, qk, N);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (!masked) xv[c] = a.x[gi + c * a.n_local];
+      if (HASK) kv = a.k[gi];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      sx[c][r] = xv[c];
+      sy[c][r] = T(0);
+    }
+    if (HASK) sk[r] = kv;
+  }
+  __syncthreads();
+
+  // 2. elements: lane -> (type, cube); 64 | C keeps the type wave-uniform
+  for (int e = tid; e < 6 * C; e += NTH) {
+    const int t = __builtin_amdgcn_readfirstlane(e / C);
+    const int c = e - t * C;
+    const int cx = c % TX, cy = (c / TX) % TY, cz = c / (TX * TY);
+    if (bx0 + cx + by0 + cy + bz0 + cz > n - kLim[t]) continue;
+    const int cb = 2 * cx + RX * (2 * cy + RY * 2 * cz);
+    const TypeGeo<T> *g = L.geo + 6 * m + t;
+    int li[10];
+#pragma unroll
+    for (int v = 0; v < 10; ++v) li[v] = cb + snoff[t][v];
+    if constexpr (KIND == P2V_EPSILON) {
+      T u[3][10], mu[10], y[3][10];
+#pragma unroll
+      for (int v = 0; v < 10; ++v) {
+        u[0][v] = sx[0][li[v]];
+        u[1][v] = sx[1][li[v]];
+        u[2][v] = sx[2][li[v]];
+        mu[v] = sk[li[v]];
+      }
+      if constexpr (MAP == 0) {
+        eps_elem(u, mu, g->grad, g->vol, y);
+      } else {
+        const MacroGeo<T> &mg = a.mgeo[m];
+        const T bc[3] = {T(bx0 + cx + kOff[t][0][0]), T(by0 + cy + kOff[t][0][1]), T(bz0 + cz + kOff[t][0][2])};
+        const T inv_n = T(1) / T(n);
+        T P0[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          P0[d] = mg.v0[d] + (mg.JM[3 * d + 0] * bc[0] + mg.JM[3 * d + 1] * bc[1] + mg.JM[3 * d + 2] * bc[2]) * inv_n;
+        eps_blended_elem(u, mu, P0, g->JT, mg.s, a.qtab, a.nq, y);
+      }
+#pragma unroll
+      for (int v = 0; v < 10; ++v)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) atomicAdd(&sy[cc][li[v]], y[cc][v]);
+    } else {
+      T u[10], kv[10], y[10];
+#pragma unroll
+      for (int v = 0; v < 10; ++v) {
+        u[v] = sx[0][li[v]];
+        if constexpr (HASK) kv[v] = sk[li[v]];
+        else kv[v] = T(1);
+      }
+      p2_elem<T, HASK>(u, kv, g->Gp, y);
+#pragma unroll
+      for (int v = 0; v < 10; ++v) atomicAdd(&sy[0][li[v]], y[v]);
+    }
+  }
+  __syncthreads();
+
+  // 3. write back: exclusive points are stored, shared face points are added
+  for (int r = tid; r < R; r += NTH) {
+    const int rx = r % RX, ry = (r / RX) % RY, rz = r / (RX * RY);
+    const int qi = 2 * bx0 + rx, qj = 2 * by0 + ry, qk = 2 * bz0 + rz;
+    if (qi + qj + qk > N) continue;
+    if (L.dirichlet && is_bnd(bnd, qi, qj, qk, N)) continue;
+    const bool excl = ((rx & 1) || ((rx > 0 || bx0 == 0) && rx < 2 * TX)) &&
+                      ((ry & 1) || ((ry > 0 || by0 == 0) && ry < 2 * TY)) &&
+                      ((rz & 1) || ((rz > 0 || bz0 == 0) && rz < 2 * TZ));
+    const int64_t gi = base + row_base(qj, qk, N) + qi;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      if (excl)
+        a.y[gi + c * a.n_local] = sy[c][r];
+      else
+        atomicAdd(a.y + gi + c * a.n_local, sy[c][r]);
+    }
+  }
+}
+
+template <typename T, int KIND, int MAP, int TX, int TY, int TZ>
+hipError_t launch_cfg(const TileArgs<T> &a, hipStream_t s) {
+  using Cfg = TileCfg<T, KIND, MAP, TX, TY, TZ>;
+  if (a.ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_tile<T, KIND, MAP, TX, TY, TZ>), dim3(a.ntiles), dim3(Cfg::NTH), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int KIND, int MAP>
+hipError_t launch_kind(const TileArgs<T> &a, int cfg, hipStream_t s) {
+  switch (cfg) {
+    case 0: return launch_cfg<T, KIND, MAP, 4, 4, 4>(a, s);
+    case 1: return launch_cfg<T, KIND, MAP, 8, 4, 2>(a, s);
+    case 2: return launch_cfg<T, KIND, MAP, 8, 4, 4>(a, s);
+    case 3: return launch_cfg<T, KIND, MAP, 4, 4, 8>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_tile_apply(const TileArgs<T> &a, int kind, int map, int cfg, hipStream_t s) {
+  switch (kind) {
+    case P2_LAPLACE: return launch_kind<T, P2_LAPLACE, 0>(a, cfg, s);
+    case P2_DIVKGRAD: return launch_kind<T, P2_DIVKGRAD, 0>(a, cfg, s);
+    case P2V_EPSILON:
+      // the epsilon tiles stage 3 components; only the smallest tile fits LDS twice per CU
+      if (cfg != 0) return hipErrorInvalidValue;
+      return map == 0 ? launch_cfg<T, P2V_EPSILON, 0, 4, 4, 4>(a, s)
+                      : launch_cfg<T, P2V_EPSILON, 1, 4, 4, 4>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_tile_apply<double>(const TileArgs<double> &, int, int, int, hipStream_t);
+template hipError_t launch_tile_apply<float>(const TileArgs<float> &, int, int, int, hipStream_t);
+
+}  // namespace tmf

@@ -1,0 +1,156 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tmf {
+
+// ---------------------------------------------------------------------------
+// The six micro-tetrahedron types of a uniformly refined macro-tetrahedron
+// (section "Hybrid Tetrahedral Grids": every micro-tet is a translate of one
+// of six reference shapes).  In the index space of the macro, a micro-cube
+// with base b holds up to six tets with these vertex offsets; type t exists
+// iff b >= 0 and b.x + b.y + b.z <= n - kLim[t].  The exclusive loop bounds of
+// the sawtooth strategy give the same counts: C(n+2,3) white-up, C(n+1,3)
+// for each of the four middle types, C(n,3) white-down.
+// Order: white-up, four octahedron types, white-down.
+constexpr int kOff[6][4][3] = {
+    {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}},
+    {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 0, 1}},
+    {{1, 0, 0}, {0, 1, 0}, {1, 1, 0}, {1, 0, 1}},
+    {{0, 1, 0}, {0, 0, 1}, {1, 0, 1}, {0, 1, 1}},
+    {{0, 1, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}},
+    {{1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {1, 1, 1}},
+};
+constexpr int kLim[6] = {1, 2, 2, 2, 2, 3};
+// local edge order of the P2 edge DoFs of a tet
+constexpr int kEdge[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+
+// The 15-point neighbourhood of a lattice vertex (itself + 14 neighbours).
+constexpr int kNb[15][3] = {
+    {0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1}, {1, -1, 0},
+    {-1, 1, 0}, {1, 0, -1}, {-1, 0, 1}, {0, 1, -1}, {0, -1, 1}, {1, -1, 1}, {-1, 1, -1},
+};
+
+constexpr int nb_slot(int dx, int dy, int dz) {
+  for (int s = 0; s < 15; ++s)
+    if (kNb[s][0] == dx && kNb[s][1] == dy && kNb[s][2] == dz) return s;
+  return -1;
+}
+
+// slot of vertex c of type t seen from vertex a of the same tet
+constexpr int vslot(int t, int a, int c) {
+  return nb_slot(kOff[t][c][0] - kOff[t][a][0], kOff[t][c][1] - kOff[t][a][1],
+                 kOff[t][c][2] - kOff[t][a][2]);
+}
+
+// Per (macro, type) constants, computed in FP64 on the host.
+//   Gp[a][b] = |T| grad(lambda_a) . grad(lambda_b)   (P1 local matrix)
+//   grad[a][d] = grad(lambda_a), vol = |T|
+//   JT = parametric Jacobian of the micro-tet (columns: edge vectors from vertex 0)
+template <typename T>
+struct TypeGeo {
+  T Gp[16];
+  T grad[12];
+  T vol;
+  T JT[9];
+  T pad[2];
+};
+
+// Per macro constants for curved maps: parametric origin and Jacobian of the
+// macro, octant sign vector.
+template <typename T>
+struct MacroGeo {
+  T v0[3];
+  T JM[9];
+  T s[3];
+  T pad;
+};
+
+// Packed tetrahedral lattice of size N: C3(M) = (M+1)(M+2)(M+3)/6 points.
+__host__ __device__ inline int c3(int M) { return (M + 1) * (M + 2) * (M + 3) / 6; }
+// storage index of the first point of row (j, k)
+__host__ __device__ inline int row_base(int j, int k, int N) {
+  const int M = N - k;
+  return c3(N) - c3(M) + (j * (2 * M + 3 - j)) / 2;
+}
+// zero pattern of the barycentric coordinates (N-i-j-k, i, j, k): bit f set iff coordinate f is 0
+__host__ __device__ inline int zero_pattern(int i, int j, int k, int N) {
+  return (N - i - j - k == 0) | ((i == 0) << 1) | ((j == 0) << 2) | ((k == 0) << 3);
+}
+
+enum Kind { P1_LAPLACE = 0, P1_DIVKGRAD = 1, P2_LAPLACE = 2, P2_DIVKGRAD = 3, P2V_EPSILON = 4 };
+
+template <typename T>
+struct LatticeArgs {
+  int n;          // micro-cubes per macro edge, 2^level
+  int N;          // lattice size of the DoF space (n or 2n)
+  int nt;         // number of macros
+  int L;          // lattice points per macro, C3(N)
+  int dirichlet;  // 1: zero boundary rows and columns
+  const uint32_t *bnd;         // per macro: bit z set if points of zero pattern z are boundary DoFs
+  const TypeGeo<T> *geo;       // per macro x 6 types
+};
+
+template <typename T>
+struct P1Args {
+  LatticeArgs<T> lat;
+  const T *w15;  // per macro: 15-point stencil of the constant-coefficient operator
+  const T *k;
+  const T *x;
+  T *y;
+};
+
+template <typename T>
+struct P1AdjArgs {
+  LatticeArgs<T> lat;
+  const T *k;
+  const T *x;
+  const T *gy;
+  T *gx;
+  T *gk;
+};
+
+template <typename T>
+struct TileArgs {
+  LatticeArgs<T> lat;
+  const int4 *tiles;  // (macro, bx0, by0, bz0) in micro-cube units
+  int ntiles;
+  int64_t n_local;    // component stride of vector fields
+  const MacroGeo<T> *mgeo;
+  const T *qtab;      // blended map: per quadrature point [w, bary(4), phi(10), refgrad(30)]
+  int nq;
+  const T *k;
+  const T *x;
+  T *y;
+};
+
+struct GroupArgs {
+  const int64_t *ptr;  // CSR of duplicate groups
+  const int64_t *idx;  // member slots, ascending
+  int64_t ngroups;
+  int64_t n_local;
+  int ncomp;
+};
+
+constexpr int kQStride = 45;  // floats per quadrature point in qtab
+
+// launchers (kernels.hip); return the HIP error of the launch
+template <typename T>
+hipError_t launch_p1_apply(const P1Args<T> &a, int kind, hipStream_t s);
+template <typename T>
+hipError_t launch_p1_adjoint(const P1AdjArgs<T> &a, hipStream_t s);
+template <typename T>
+hipError_t launch_tile_apply(const TileArgs<T> &a, int kind, int map, int tile_cfg, hipStream_t s);
+template <typename T>
+hipError_t launch_interface_sum(const GroupArgs &g, T *y, hipStream_t s);
+template <typename T>
+hipError_t launch_fill(T *p, int64_t n, T v, hipStream_t s);
+
+// tile shapes available to the element-centric kernels (micro-cubes per tile)
+constexpr int kNumTileCfg = 4;
+constexpr int kTileCfg[kNumTileCfg][3] = {{4, 4, 4}, {8, 4, 2}, {8, 4, 4}, {4, 4, 8}};
+
+}  // namespace tmf
