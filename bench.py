@@ -1,0 +1,311 @@
+#!/usr/bin/env python3
+"""Benchmark: matrix-free finite-element operator apply on one MI355X.
+
+Headline workload (one "step" = one operator application y = A(k) x, the
+whole apply path: zero fill, element kernel, interface sum, boundary mask):
+the P2 variable-coefficient diffusion operator -div(k grad) (equation P2V) in
+FP64 on the unit cube split into 6 macro-tetrahedra, refinement level 6
+(2,146,689 DoFs), k = 1 + 0.5 sin(2 pi x) cos(2 pi y) z interpolated at the
+nodes, x ~ U[-1,1] hashed from the DoF keys (seed 2), homogeneous Dirichlet
+rows and columns.  Inputs are resident in HBM before timing starts.
+
+Also reported under "forms": the other operators and precisions on their
+workloads (P1 Laplacian at levels 4 and 9, the P1 div(k grad) forward and
+fused adjoint at levels 7 and 9, the P2 FP32 apply, the vector epsilon
+operator on the radially blended shell in FP64 and FP32).
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+"""
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12       # B/s, MI355X HBM3E
+PEAK_FP64 = 78.6e12     # FLOP/s, vector FP64
+PEAK_FP32 = 157.3e12    # FLOP/s, vector FP32
+
+# Arithmetic of each kernel's formulation, counted from the source (add, sub,
+# mul = 1 flop, fused multiply-add = 2), per unit the kernel processes.
+FLOPS = {
+    "p2_divkgrad": 358,        # per micro-tet: gradient coefficients, h, exact k-weights, sigma, outputs
+    "p2_laplace": 184,         # per micro-tet: same without the coefficient weights
+    "p1_laplace": 30,          # per DoF: 15-point stencil
+    "p1_divkgrad": 312,        # per DoF: 24 incident micro-tets x (4x4 row, mean k, accumulate)
+    "p1_adjoint": 1200,        # per DoF: forward row (312) + 24 x bilinear form (37)
+    "eps_affine": 970,         # per micro-tet
+    "eps_blended_per_q": 657,  # per micro-tet and quadrature point (map Jacobian, inverse, 2 x 90-term contractions)
+}
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=100)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--main-only", action="store_true", help="skip the other forms")
+    p.add_argument("--form-steps", type=int, default=20)
+    return p.parse_args()
+
+
+class Hip:
+    """HIP events through the runtime PyTorch loaded (same process-wide instance)."""
+
+    def __init__(self):
+        self.L = ctypes.CDLL("libamdhip64.so.7")
+        self.L.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.L.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.L.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                               ctypes.c_void_p]
+
+    def event(self):
+        e = ctypes.c_void_p()
+        if self.L.hipEventCreate(ctypes.byref(e)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+        return e
+
+    def elapsed_ms(self, a, b):
+        f = ctypes.c_float()
+        if self.L.hipEventElapsedTime(ctypes.byref(f), a, b) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return f.value
+
+    def destroy(self, e):
+        self.L.hipEventDestroy(e)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def device_inputs(mesh, op, seed, torch, kind_family):
+    import workloads as W
+    info = mesh.dof_info(op.space, owner=False, boundary=False)
+    keys, xyz = info["keys"], info["xyz"]
+    x = np.concatenate([W.uniform_from_keys(seed, keys, stream=c) for c in range(op.ncomp)])
+    if kind_family == "p2_divkgrad":
+        k = W.fields.cube_k(xyz)
+    elif kind_family == "p1_divkgrad":
+        k = W.fields.perturbed_k(keys, 5)
+    elif kind_family == "eps":
+        k = W.fields.shell_mu(keys, xyz, 3)
+    else:
+        k = None
+    dt = op.dtype
+    xt = torch.tensor(x, dtype=dt, device="cuda")
+    kt = torch.tensor(k, dtype=dt, device="cuda") if k is not None else None
+    return xt, kt
+
+
+def time_apply(op, x, k, y, steps, warmup, hip, torch, fn=None):
+    """Warm up, then time exactly `steps` applies; returns (wall ms/step, kernel ms mean)."""
+    import paper_2404_08371_amd as T
+    L = T.lib()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    pk = ctypes.c_void_p(k.data_ptr()) if k is not None else None
+    px, py = ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr())
+    for _ in range(warmup):
+        T.check(L.tmf_apply(op.handle, pk, px, py, stream)) if fn is None else fn(None, None)
+    evs = [(hip.event(), hip.event()) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b, a in evs:
+        if fn is None:
+            T.check(L.tmf_apply_timed(op.handle, pk, px, py, stream, b, a))
+        else:
+            fn(b, a)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    kern = float(np.mean([hip.elapsed_ms(b, a) for b, a in evs]))
+    for b, a in evs:
+        hip.destroy(b)
+        hip.destroy(a)
+    return wall, kern
+
+
+def n_elements(mesh_nt, level):
+    n = 2 ** level
+    return mesh_nt * n ** 3
+
+
+def traffic_for(kernel_key):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they match the current source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    ent = data.get(kernel_key)
+    if not ent:
+        return None
+    src = os.path.join(ROOT, "paper_2404_08371_amd", "csrc", ent["source"])
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if h != ent.get("source_sha256_16"):
+        return None
+    return ent["bytes_per_launch"]
+
+
+def cpu_baseline_c2():
+    """The oracle, as it stands, on one full apply of the headline workload (host cores)."""
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    import workloads as W
+    v, t = W.meshes.kuhn_cube()
+    with threadpool_limits(1):
+        pr = O.Problem(v, t, 6, O.P2_DIVKGRAD, O.BC_DIRICHLET_ZERO)
+        x = W.uniform_from_keys(2, pr.keys)
+        k = W.fields.cube_k(pr.xyz)
+        t0 = time.perf_counter()
+        pr.apply(x, k)
+        dt = time.perf_counter() - t0
+    return {"value": pr.n_unique / dt / 1e6, "unit": "MDoF/s", "cores": 1, "kind": "oracle",
+            "sample": "one full FP64 apply of the headline workload (Kuhn cube, level 6, %d DoFs), "
+                      "numpy oracle single-threaded, setup excluded; %.1f s" % (pr.n_unique, dt)}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (sharding by "
+              "macro-tetrahedra is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2404_08371_amd as T
+    import workloads as W
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    hip = Hip()
+    torch.manual_seed(0)
+
+    # ------------------------------------------------------------ headline
+    log("headline: P2 div(k grad) FP64, Kuhn cube level 6")
+    v, t = W.meshes.kuhn_cube()
+    mesh = T.Mesh(v, t, 6)
+    op = T.Operator(mesh, T.P2_DIVKGRAD, T.F64, T.BC_DIRICHLET_ZERO)
+    x, k = device_inputs(mesh, op, 2, torch, "p2_divkgrad")
+    y = torch.empty_like(x)
+    cfg, ms = ctypes.c_int(), ctypes.c_float()
+    T.check(T.lib().tmf_op_autotune(op.handle, ctypes.c_void_p(k.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                    ctypes.c_void_p(y.data_ptr()),
+                                    ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), 10,
+                                    ctypes.byref(cfg), ctypes.byref(ms)))
+    tx, ty, tz = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    T.check(T.lib().tmf_op_tile_shape(op.handle, cfg.value, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(tz)))
+    log("autotuned tile", (tx.value, ty.value, tz.value), "%.4f ms" % ms.value)
+    wall, kern = time_apply(op, x, k, y, args.steps, args.warmup, hip, torch)
+    nel = n_elements(6, 6)
+    flops = nel * FLOPS["p2_divkgrad"]
+    bytes_alg = 3 * op.n_local * 8
+    t_alu, t_hbm = flops / PEAK_FP64, bytes_alg / PEAK_HBM
+    bound = "alu" if t_alu >= t_hbm else "hbm"
+    if bound == "alu":
+        achieved, peak, unit = flops / (kern * 1e-3) / 1e12, PEAK_FP64 / 1e12, "TFLOP/s"
+    else:
+        achieved, peak, unit = bytes_alg / (kern * 1e-3) / 1e9, PEAK_HBM / 1e9, "GB/s"
+    traffic = traffic_for("p2_divkgrad_fp64_cube6")
+    value = op.n_unique / (wall * 1e-3) / 1e6
+    out = {
+        "metric": "operator-apply MDoF/s (FP64 vs FP32-refined, fwd+adjoint) and % HBM roofline",
+        "value": round(value, 2), "unit": "MDoF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "P2 -div(k grad) apply, FP64, unit cube as 6 macro-tets, level 6, "
+                               "k=1+0.5 sin(2 pi x)cos(2 pi y)z nodal, Dirichlet, x~U[-1,1] seed 2",
+                   "dofs": op.n_unique, "local_slots": op.n_local, "micro_tets": nel,
+                   "tile": [tx.value, ty.value, tz.value], "parallelism": "single GPU"},
+        "roofline": {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+                     "frac": round(achieved / peak, 4), "traffic": traffic,
+                     "kernel_ms": round(kern, 5), "flops_per_launch": flops,
+                     "alg_bytes_per_launch": bytes_alg,
+                     "hbm_frac": round(bytes_alg / (kern * 1e-3) / PEAK_HBM, 4)},
+    }
+    log("headline %.1f MDoF/s, kernel %.4f ms, step %.4f ms" % (value, kern, wall))
+
+    # --------------------------------------------------------------- forms
+    if not args.main_only:
+        forms = {}
+
+        def form(name, mesh, op, fam, seed, flops_launch, bytes_launch, peak_flops, steps, adjoint=False):
+            xx, kk = device_inputs(mesh, op, seed, torch, fam)
+            yy = torch.empty_like(xx)
+            if op.space == 2:
+                c2, m2 = ctypes.c_int(), ctypes.c_float()
+                T.check(T.lib().tmf_op_autotune(op.handle, ctypes.c_void_p(kk.data_ptr()) if kk is not None else None,
+                                                ctypes.c_void_p(xx.data_ptr()), ctypes.c_void_p(yy.data_ptr()),
+                                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), 3,
+                                                ctypes.byref(c2), ctypes.byref(m2)))
+            fn = None
+            if adjoint:
+                gk = torch.empty_like(kk)
+                gy = xx.clone()
+                L = T.lib()
+                st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+                def fn(b, a):
+                    if b is not None:
+                        hip.L.hipEventRecord(b, st)
+                    T.check(L.tmf_apply_adjoint(op.handle, ctypes.c_void_p(kk.data_ptr()),
+                                                ctypes.c_void_p(xx.data_ptr()), ctypes.c_void_p(gy.data_ptr()),
+                                                ctypes.c_void_p(yy.data_ptr()), ctypes.c_void_p(gk.data_ptr()), st))
+                    if a is not None:
+                        hip.L.hipEventRecord(a, st)
+            w, kms = time_apply(op, xx, kk, yy, steps, 3, hip, torch, fn)
+            r = {"dofs": op.n_unique * op.ncomp, "mdofs": round(op.n_unique * op.ncomp / (w * 1e-3) / 1e6, 2),
+                 "ms_per_apply": round(w, 5), "kernel_ms": round(kms, 5),
+                 "hbm_frac": round(bytes_launch / (kms * 1e-3) / PEAK_HBM, 4),
+                 "alu_frac": round(flops_launch / (kms * 1e-3) / peak_flops, 4)}
+            forms[name] = r
+            log(name, r)
+            del xx, kk, yy
+
+        hip.L.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        vr, tr = W.meshes.ref_tet()
+        for lvl in (4, 9):
+            m1 = T.Mesh(vr, tr, lvl)
+            o1 = T.Operator(m1, T.P1_LAPLACE, T.F64)
+            form("p1_laplace_fp64_reftet_l%d" % lvl, m1, o1, "p1", 1, o1.n_local * FLOPS["p1_laplace"],
+                 16 * o1.n_local, PEAK_FP64, args.form_steps)
+        for lvl in (7, 9):
+            m1 = T.Mesh(vr, tr, lvl)
+            o1 = T.Operator(m1, T.P1_DIVKGRAD, T.F64)
+            form("p1_divkgrad_fwd_fp64_reftet_l%d" % lvl, m1, o1, "p1_divkgrad", 6,
+                 o1.n_local * FLOPS["p1_divkgrad"], 24 * o1.n_local, PEAK_FP64, args.form_steps)
+            form("p1_divkgrad_adjoint_fp64_reftet_l%d" % lvl, m1, o1, "p1_divkgrad", 6,
+                 o1.n_local * FLOPS["p1_adjoint"], 40 * o1.n_local, PEAK_FP64, args.form_steps, adjoint=True)
+        o32 = T.Operator(mesh, T.P2_DIVKGRAD, T.F32)
+        form("p2_divkgrad_fp32_cube_l6", mesh, o32, "p2_divkgrad", 2, nel * FLOPS["p2_divkgrad"],
+             12 * o32.n_local, PEAK_FP32, args.form_steps)
+        m7 = T.Mesh(v, t, 7)
+        o7 = T.Operator(m7, T.P2_DIVKGRAD, T.F64)
+        form("p2_divkgrad_fp64_cube_l7", m7, o7, "p2_divkgrad", 2, n_elements(6, 7) * FLOPS["p2_divkgrad"],
+             24 * o7.n_local, PEAK_FP64, args.form_steps)
+        del o7, m7
+        vs, ts = W.meshes.octahedral_shell()
+        ms6 = T.Mesh(vs, ts, 6, T.MAP_SHELL_RADIAL)
+        rule = W.quadrature.rule_degree5()
+        for prec, nm, pk, bpd in ((T.F64, "fp64", PEAK_FP64, 8), (T.F32, "fp32", PEAK_FP32, 4)):
+            oe = T.Operator(ms6, T.P2V_EPSILON, prec, T.BC_DIRICHLET_ZERO, rule=rule)
+            form("eps_blended_%s_shell_l6" % nm, ms6, oe, "eps", 4,
+                 n_elements(24, 6) * 14 * FLOPS["eps_blended_per_q"], 7 * bpd * oe.n_local, pk, 5)
+            del oe
+        out["forms"] = forms
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline_c2()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

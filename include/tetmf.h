@@ -180,6 +180,31 @@ tmf_status tmf_apply(tmf_op *op, const void *coeff, const void *x, void *y, tmf_
 tmf_status tmf_apply_adjoint(tmf_op *op, const void *coeff, const void *x, const void *gy,
                              void *gx, void *gk, tmf_stream stream);
 
+/* Same as tmf_apply, and additionally records the caller-created hipEvent_t
+ * `ev_before` on `stream` immediately before the operator's main compute
+ * kernel and `ev_after` immediately after it (fills and interface sums
+ * outside), so that the kernel's own duration can be measured.  Either event
+ * may be NULL. */
+tmf_status tmf_apply_timed(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream,
+                           void *ev_before, void *ev_after);
+
+/* Tile shapes of the element-centric (P2, epsilon) kernels.  Each shape is a
+ * box of micro-cubes staged in LDS by one workgroup; tmf_op_num_tiles gives
+ * the number of shapes valid for the op's kind (1 for P1 kinds, whose
+ * kernels are vertex-centric), tmf_op_tile_shape the cubes per box edge. */
+tmf_status tmf_op_num_tiles(const tmf_op *op, int *count);
+tmf_status tmf_op_tile_shape(const tmf_op *op, int cfg, int *tx, int *ty, int *tz);
+tmf_status tmf_op_set_tile(tmf_op *op, int cfg);
+tmf_status tmf_op_get_tile(const tmf_op *op, int *cfg);
+
+/* Autotuner: times `reps` applies of every valid tile shape on the given
+ * (caller-owned, device) inputs with HIP events, keeps the fastest shape on
+ * the op and returns it with its mean time per apply.  Synchronises the
+ * stream; overwrites y.  Every shape computes the same operator (parity is
+ * tested per shape); results differ only by floating-point summation order. */
+tmf_status tmf_op_autotune(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream,
+                           int reps, int *best_cfg, float *best_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,6 +30,14 @@ SIGNATURES = [
     ("tmf_op_info", c_int, [c_vp, c_i64p, c_i64p, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
     ("tmf_apply", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     ("tmf_apply_adjoint", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    ("tmf_apply_timed", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    ("tmf_op_num_tiles", c_int, [c_vp, ctypes.POINTER(c_int)]),
+    ("tmf_op_tile_shape", c_int, [c_vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                                  ctypes.POINTER(c_int)]),
+    ("tmf_op_set_tile", c_int, [c_vp, c_int]),
+    ("tmf_op_get_tile", c_int, [c_vp, ctypes.POINTER(c_int)]),
+    ("tmf_op_autotune", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(c_int),
+                                ctypes.POINTER(ctypes.c_float)]),
 ]
 
 OPTIONAL = set()
@@ -52,6 +60,10 @@ def path():
 def lib():
     global _LIB
     if _LIB is None:
+        # PyTorch ships its own HIP runtime with the same SONAME; loading it
+        # first makes the library bind to that single runtime instance, so
+        # torch streams, events and allocations are valid handles for it.
+        import torch  # noqa: F401
         if not os.path.exists(_PATH):
             raise RuntimeError("libtetmf.so is not built (%s); run `python -m paper_2404_08371_amd.build`"
                                % _PATH)

@@ -585,7 +585,8 @@ GroupArgs group_args(const tmf_op *op) {
 }
 
 template <typename T>
-hipError_t apply_t(tmf_op *op, const void *coeff, const void *x, void *y, hipStream_t s) {
+hipError_t apply_t(tmf_op *op, const void *coeff, const void *x, void *y, hipStream_t s,
+                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
   hipError_t e;
   T *yy = static_cast<T *>(y);
   if (op->space == 1) {
@@ -595,7 +596,9 @@ hipError_t apply_t(tmf_op *op, const void *coeff, const void *x, void *y, hipStr
     a.k = static_cast<const T *>(coeff);
     a.x = static_cast<const T *>(x);
     a.y = yy;
+    if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
     e = launch_p1_apply<T>(a, op->kind, s);
+    if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
   } else {
     e = launch_fill<T>(yy, op->ncomp * op->n_local, T(0), s);
     if (e != hipSuccess) return e;
@@ -610,7 +613,9 @@ hipError_t apply_t(tmf_op *op, const void *coeff, const void *x, void *y, hipStr
     a.k = static_cast<const T *>(coeff);
     a.x = static_cast<const T *>(x);
     a.y = yy;
+    if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
     e = launch_tile_apply<T>(a, op->kind, op->mesh->map, op->tile_cfg, s);
+    if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
   }
   if (e != hipSuccess) return e;
   return launch_interface_sum<T>(group_args(op), yy, s);
@@ -638,16 +643,106 @@ hipError_t adjoint_t(tmf_op *op, const void *coeff, const void *x, const void *g
 
 extern "C" {
 
-tmf_status tmf_apply(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream) {
+static tmf_status check_apply(tmf_op *op, const void *coeff, const void *x, void *y) {
   if (!op) return fail(TMF_EINVAL, "op is NULL");
   if (!x || !y) return fail(TMF_EINVAL, "x or y is NULL");
   if (has_coeff(op->kind) != (coeff != nullptr))
     return fail(TMF_EINVAL, has_coeff(op->kind) ? "this operator needs a coefficient field"
                                                 : "this operator takes no coefficient field");
   if (y == x || (coeff && y == coeff)) return fail(TMF_EINVAL, "y must not alias x or the coefficient");
+  return TMF_OK;
+}
+
+tmf_status tmf_apply_timed(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream,
+                           void *ev_before, void *ev_after) {
+  tmf_status st = check_apply(op, coeff, x, y);
+  if (st != TMF_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = op->prec == TMF_F64 ? apply_t<double>(op, coeff, x, y, s) : apply_t<float>(op, coeff, x, y, s);
+  hipEvent_t e0 = static_cast<hipEvent_t>(ev_before), e1 = static_cast<hipEvent_t>(ev_after);
+  hipError_t e = op->prec == TMF_F64 ? apply_t<double>(op, coeff, x, y, s, e0, e1)
+                                     : apply_t<float>(op, coeff, x, y, s, e0, e1);
   if (e != hipSuccess) return hip_fail(e, "apply launch");
+  return TMF_OK;
+}
+
+tmf_status tmf_apply(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream) {
+  return tmf_apply_timed(op, coeff, x, y, stream, nullptr, nullptr);
+}
+
+static int num_tiles(const tmf_op *op) {
+  if (op->space == 1) return 1;
+  return op->kind == TMF_P2V_EPSILON ? 1 : kNumTileCfg;
+}
+
+tmf_status tmf_op_num_tiles(const tmf_op *op, int *count) {
+  if (!op || !count) return fail(TMF_EINVAL, "NULL argument");
+  *count = num_tiles(op);
+  return TMF_OK;
+}
+
+tmf_status tmf_op_tile_shape(const tmf_op *op, int cfg, int *tx, int *ty, int *tz) {
+  if (!op) return fail(TMF_EINVAL, "op is NULL");
+  if (cfg < 0 || cfg >= num_tiles(op)) return fail(TMF_EINVAL, "tile shape %d out of range", cfg);
+  if (tx) *tx = op->space == 1 ? 1 : kTileCfg[cfg][0];
+  if (ty) *ty = op->space == 1 ? 1 : kTileCfg[cfg][1];
+  if (tz) *tz = op->space == 1 ? 1 : kTileCfg[cfg][2];
+  return TMF_OK;
+}
+
+tmf_status tmf_op_set_tile(tmf_op *op, int cfg) {
+  if (!op) return fail(TMF_EINVAL, "op is NULL");
+  if (cfg < 0 || cfg >= num_tiles(op)) return fail(TMF_EINVAL, "tile shape %d out of range", cfg);
+  op->tile_cfg = cfg;
+  return TMF_OK;
+}
+
+tmf_status tmf_op_get_tile(const tmf_op *op, int *cfg) {
+  if (!op || !cfg) return fail(TMF_EINVAL, "NULL argument");
+  *cfg = op->tile_cfg;
+  return TMF_OK;
+}
+
+tmf_status tmf_op_autotune(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream, int reps,
+                           int *best_cfg, float *best_ms) {
+  tmf_status st = check_apply(op, coeff, x, y);
+  if (st != TMF_OK) return st;
+  if (reps < 1) return fail(TMF_EINVAL, "reps must be >= 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(TMF_EDEVICE, "hipEventCreate failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(TMF_EDEVICE, "hipEventCreate failed");
+  }
+  int best = op->tile_cfg;
+  float best_t = 0;
+  const int keep = op->tile_cfg;
+  for (int cfg = 0; cfg < num_tiles(op) && st == TMF_OK; ++cfg) {
+    op->tile_cfg = cfg;
+    for (int w = 0; w < 2 && st == TMF_OK; ++w) st = tmf_apply(op, coeff, x, y, stream);
+    if (st != TMF_OK) break;
+    hipError_t e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && st == TMF_OK && e == hipSuccess; ++r) st = tmf_apply(op, coeff, x, y, stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) st = hip_fail(e, "autotune timing");
+    ms /= reps;
+    if (st == TMF_OK && (cfg == 0 || ms < best_t)) {
+      best_t = ms;
+      best = cfg;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != TMF_OK) {
+    op->tile_cfg = keep;
+    return st;
+  }
+  op->tile_cfg = best;
+  if (best_cfg) *best_cfg = best;
+  if (best_ms) *best_ms = best_t;
   return TMF_OK;
 }
 
