@@ -171,12 +171,27 @@ tmf_status tmf_op_info(const tmf_op *op, int64_t *n_local, int64_t *n_unique, in
  * x, y: ncomp * n_local values; y must not alias x or coeff. */
 tmf_status tmf_apply(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream);
 
-/* Reverse-mode derivative of y = A(k) x for TMF_P1_DIVKGRAD (FP64 or FP32):
- * given gy = dL/dy, writes gx = A(k)^T gy = A(k) gy (the operator, D A D
- * included, is symmetric) and, if gk != NULL, gk_m = dL/dk_m = gy . (dA/dk_m) x
- * for every coefficient DoF m, on every copy.  All pointers are device
- * arrays of n_local values; gx and gk must not alias each other or any input.
- * Other kinds return TMF_EUNSUPPORTED. */
+/* The macro-local part of the apply: y = sum over macros M of the sum over
+ * micro-tets T of M of P_T A_T R_T x, i.e. tmf_apply without the final
+ * interface sum.  On a DoF shared by several macros each copy holds only its
+ * own macro's partial sum (x is read copy by copy).  tmf_apply is
+ * tmf_apply_local followed by tmf_interface_sum. */
+tmf_status tmf_apply_local(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream);
+
+/* In place, v <- S v: every copy of a shared DoF receives the sum over its
+ * copies (ncomp * n_local values of the op's precision; copies added in
+ * ascending slot order).  No-op on single-macro meshes. */
+tmf_status tmf_interface_sum(tmf_op *op, void *v, tmf_stream stream);
+
+/* Reverse mode of the macro-local apply of TMF_P1_DIVKGRAD (FP64 or FP32).
+ * With y = L(k) x the local apply (boundary masking included), given gy:
+ *   gx = L(k)^T gy = L(k) gy,
+ *   gk_m = gy . (dL/dk_m) x   for every coefficient slot m (copy by copy),
+ * gk written only if non-NULL.  The transpose of the full apply y = S L(k) x
+ * is therefore: tmf_interface_sum on (a copy of) dL/dy, then this call.  For
+ * a single macro S = I.  All pointers are device arrays of n_local values; gx
+ * and gk must not alias each other or any input.  Other kinds return
+ * TMF_EUNSUPPORTED. */
 tmf_status tmf_apply_adjoint(tmf_op *op, const void *coeff, const void *x, const void *gy,
                              void *gx, void *gk, tmf_stream stream);
 
@@ -204,6 +219,71 @@ tmf_status tmf_op_get_tile(const tmf_op *op, int *cfg);
  * tested per shape); results differ only by floating-point summation order. */
 tmf_status tmf_op_autotune(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream,
                            int reps, int *best_cfg, float *best_ms);
+
+/* ---------------------------------------------------------------- batches
+ * A batch applies `count` operator instances in one persistent launch of the
+ * element kernel (instances may have different meshes, levels and
+ * coefficients).  All operators must be P2 kinds (TMF_P2_LAPLACE,
+ * TMF_P2_DIVKGRAD or TMF_P2V_EPSILON) of one kind and one precision on affine
+ * meshes; they must outlive the batch.  Vectors are concatenated: instance i
+ * occupies [offsets[i], offsets[i+1]) with its own layout inside (components
+ * of vector fields consecutive).  Errors: TMF_EINVAL (NULL, duplicate or
+ * mismatched operators), TMF_EUNSUPPORTED (P1 kind, curved map), TMF_ENOMEM. */
+tmf_status tmf_batch_create(tmf_op *const *ops, int count, tmf_batch **out);
+void tmf_batch_destroy(tmf_batch *batch);
+/* count and, if offsets != NULL, the count + 1 offsets (host array). */
+tmf_status tmf_batch_info(const tmf_batch *batch, int *count, int64_t *offsets);
+/* y = A_i(coeff_i) x_i for every instance i with active[i] != 0 (device byte
+ * array, or NULL for all); y of inactive instances is set to 0.  Same rules as
+ * tmf_apply (asynchronous on `stream`, no allocation, capturable). */
+tmf_status tmf_batch_apply(tmf_batch *batch, const void *coeff, const void *x, void *y, const uint8_t *active,
+                           tmf_stream stream);
+/* tmf_batch_apply with events around the element kernel (see tmf_apply_timed). */
+tmf_status tmf_batch_apply_timed(tmf_batch *batch, const void *coeff, const void *x, void *y,
+                                 const uint8_t *active, tmf_stream stream, void *ev_before, void *ev_after);
+tmf_status tmf_batch_set_tile(tmf_batch *batch, int cfg);
+/* Autotuner over the tile shapes for the whole batch (as tmf_op_autotune). */
+tmf_status tmf_batch_autotune(tmf_batch *batch, const void *coeff, const void *x, void *y, tmf_stream stream,
+                              int reps, int *best_cfg, float *best_ms);
+
+/* ------------------------------------------------ mixed-precision solver
+ * Iterative refinement for A_i x_i = b_i over a batch: outer iterations in
+ * FP64 (r = b - A x with the FP64 batch, norms, x += |r| d), inner
+ * conjugate-gradient corrections A d = r / |r| with the FP32 batch and
+ * FP64-accumulated dot products, started from d = 0 and stopped per instance
+ * at |r_inner| <= inner_rtol |r_inner,0| or inner_maxit iterations.  Blocks of
+ * graph_iters inner iterations are captured once into a HIP graph and
+ * replayed (use_graph = 0 runs the same kernels eagerly).  An instance stops
+ * when |b - A x| <= tol |b| (2-norms over distinct DoFs). */
+typedef struct tmf_ir tmf_ir;
+typedef struct {
+  double tol;         /* outer relative residual, e.g. 1e-10 */
+  int max_outer;      /* outer steps */
+  double inner_rtol;  /* inner relative residual, e.g. 1e-4 */
+  int inner_maxit;    /* inner iterations per outer step */
+  int graph_iters;    /* inner iterations per graph launch */
+  int use_graph;      /* 1: replay a captured HIP graph */
+} tmf_ir_options;
+typedef struct {
+  int outer;           /* outer refinement steps taken */
+  int inner_total;     /* inner iterations, summed over outer steps (max over instances) */
+  int graph_launches;  /* graph replays */
+  int converged;       /* 1 if every instance reached tol */
+  double seconds;      /* wall time of the solve */
+} tmf_ir_stats;
+/* Both batches hold the same instances (same meshes and boundary conditions),
+ * b64 in FP64 and b32 in FP32, scalar kinds only; opt may be NULL for the
+ * defaults {1e-10, 30, 1e-4, 2000, 16, 1}.  Allocates the device workspace
+ * (6 vectors of the batch length) and a private stream. */
+tmf_status tmf_ir_create(tmf_batch *b64, tmf_batch *b32, const tmf_ir_options *opt, tmf_ir **out);
+void tmf_ir_destroy(tmf_ir *solver);
+/* Solve in place: x (device, FP64, initial guess on entry), b (device, FP64),
+ * coefficients in FP64 and FP32 (device; NULL for constant-coefficient kinds).
+ * Ordered after the work already queued on `stream`; blocks until done.
+ * relres (host, count doubles, may be NULL) receives the final FP64 relative
+ * residuals.  Returns TMF_ENOTCONV if max_outer steps were not enough. */
+tmf_status tmf_ir_solve(tmf_ir *solver, const double *coeff64, const float *coeff32, const double *b, double *x,
+                        tmf_ir_stats *stats, double *relres, tmf_stream stream);
 
 #ifdef __cplusplus
 }

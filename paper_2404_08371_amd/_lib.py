@@ -31,6 +31,8 @@ SIGNATURES = [
     ("tmf_apply", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     ("tmf_apply_adjoint", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     ("tmf_apply_timed", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    ("tmf_apply_local", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
+    ("tmf_interface_sum", c_int, [c_vp, c_vp, c_vp]),
     ("tmf_op_num_tiles", c_int, [c_vp, ctypes.POINTER(c_int)]),
     ("tmf_op_tile_shape", c_int, [c_vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
                                   ctypes.POINTER(c_int)]),
@@ -38,6 +40,17 @@ SIGNATURES = [
     ("tmf_op_get_tile", c_int, [c_vp, ctypes.POINTER(c_int)]),
     ("tmf_op_autotune", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(c_int),
                                 ctypes.POINTER(ctypes.c_float)]),
+    ("tmf_batch_create", c_int, [ctypes.POINTER(c_vp), c_int, ctypes.POINTER(c_vp)]),
+    ("tmf_batch_destroy", None, [c_vp]),
+    ("tmf_batch_info", c_int, [c_vp, ctypes.POINTER(c_int), c_i64p]),
+    ("tmf_batch_apply", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    ("tmf_batch_apply_timed", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    ("tmf_batch_set_tile", c_int, [c_vp, c_int]),
+    ("tmf_batch_autotune", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(c_int),
+                                   ctypes.POINTER(ctypes.c_float)]),
+    ("tmf_ir_create", c_int, [c_vp, c_vp, c_vp, ctypes.POINTER(c_vp)]),
+    ("tmf_ir_destroy", None, [c_vp]),
+    ("tmf_ir_solve", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(ctypes.c_double), c_vp]),
 ]
 
 OPTIONAL = set()

@@ -20,12 +20,11 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../include/tetmf.h"
-#include "tmf_internal.h"
+#include "host_internal.h"
 
 using namespace tmf;
 
-namespace {
+namespace tmf {
 
 thread_local std::string g_err;
 
@@ -42,6 +41,10 @@ tmf_status fail(tmf_status code, const char *fmt, ...) {
 tmf_status hip_fail(hipError_t e, const char *what) {
   return fail(TMF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
+
+}  // namespace tmf
+
+namespace {
 
 using Key = std::array<int64_t, 8>;
 struct KeyHash {
@@ -70,26 +73,6 @@ Key point_key(const int64_t g[4], int i, int j, int k, int N) {
   return key;
 }
 
-template <typename T>
-struct DevBuf {
-  T *p = nullptr;
-  size_t n = 0;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
-  }
-  tmf_status upload(const void *src, size_t count) {
-    n = count;
-    if (count == 0) return TMF_OK;
-    if (hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T)) != hipSuccess) {
-      p = nullptr;
-      return fail(TMF_ENOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
-    }
-    hipError_t e = hipMemcpy(p, src, count * sizeof(T), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
-    return TMF_OK;
-  }
-};
-
 void inv3(const double J[9], double Ji[9], double *det) {
   Ji[0] = J[4] * J[8] - J[5] * J[7];
   Ji[1] = J[2] * J[7] - J[1] * J[8];
@@ -106,26 +89,7 @@ void inv3(const double J[9], double Ji[9], double *det) {
 
 }  // namespace
 
-// ------------------------------------------------------------------ mesh
-struct SpaceLayout {
-  bool built = false;
-  int N = 0;
-  int64_t L = 0, n_local = 0, n_unique = 0;
-  std::vector<int64_t> gptr, gidx;  // duplicate groups (size >= 2), members ascending
-  std::vector<uint8_t> owner;
-};
-
-struct tmf_mesh {
-  int level = 0, n = 1, map = 0;
-  int64_t nv = 0, nt = 0;
-  std::vector<double> V;
-  std::vector<int64_t> T;
-  std::vector<uint32_t> bnd;  // per macro: boundary bit per zero pattern
-  std::vector<double> sgn;    // per macro octant signs (shell map)
-  SpaceLayout sp[3];
-};
-
-static void build_layout(tmf_mesh *m, int space) {
+void tmf_build_layout(tmf_mesh *m, int space) {
   SpaceLayout &S = m->sp[space];
   if (S.built) return;
   S.N = m->n * space;
@@ -289,7 +253,7 @@ tmf_status tmf_mesh_layout(const tmf_mesh *mesh, int space, int64_t *n_local, in
   if (space != 1 && space != 2) return fail(TMF_EINVAL, "space must be 1 or 2");
   if (space == 2 && mesh->level > TMF_MAX_LEVEL_P2)
     return fail(TMF_EINVAL, "P2 space supports level <= %d", TMF_MAX_LEVEL_P2);
-  build_layout(const_cast<tmf_mesh *>(mesh), space);
+  tmf_build_layout(const_cast<tmf_mesh *>(mesh), space);
   if (n_local) *n_local = mesh->sp[space].n_local;
   if (n_unique) *n_unique = mesh->sp[space].n_unique;
   return TMF_OK;
@@ -334,24 +298,8 @@ tmf_status tmf_mesh_dof_info(const tmf_mesh *mesh, int space, int64_t *keys, dou
 
 }  // extern "C"
 
-// -------------------------------------------------------------- operator
-struct tmf_op {
-  const tmf_mesh *mesh = nullptr;
-  int kind = 0, prec = 0, bc = 0, space = 1, ncomp = 1, N = 1, nq = 0;
-  int64_t L = 0, n_local = 0, n_unique = 0;
-  int tile_cfg = 0;
-  DevBuf<uint8_t> geo, w15, mgeo, qtab;
-  DevBuf<uint32_t> bnd;
-  DevBuf<int4> tiles[kNumTileCfg];
-  int ntiles[kNumTileCfg] = {0};
-  DevBuf<int64_t> gptr, gidx;
-  int64_t ngroups = 0;
-  DevBuf<uint8_t> owner;
-};
-
 namespace {
 
-bool has_coeff(int kind) { return kind == TMF_P1_DIVKGRAD || kind == TMF_P2_DIVKGRAD || kind == TMF_P2V_EPSILON; }
 
 template <typename T>
 void fill_geometry(const tmf_mesh *m, std::vector<TypeGeo<T>> &geo, std::vector<T> &w15,
@@ -474,7 +422,7 @@ tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const
     return fail(TMF_EINVAL, "affine operators are integrated exactly: pass no quadrature rule");
   }
   tmf_mesh *mm = const_cast<tmf_mesh *>(mesh);
-  build_layout(mm, space);
+  tmf_build_layout(mm, space);
   const SpaceLayout &S = mesh->sp[space];
 
   auto *op = new (std::nothrow) tmf_op;
@@ -527,9 +475,18 @@ tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const
       for (int64_t mac = 0; mac < mesh->nt; ++mac)
         for (int bz = 0; bz < n; bz += TZ)
           for (int by = 0; by < n - bz; by += TY)
-            for (int bx = 0; bx < n - bz - by; bx += TX) tl.push_back(make_int4(int(mac), bx, by, bz));
+            for (int bx = 0; bx < n - bz - by; bx += TX) tl.push_back(make_int4(0, int(mac), pack_base(bx, by, bz), 0));
       op->ntiles[cfg] = static_cast<int>(tl.size());
       st = op->tiles[cfg].upload(tl.data(), tl.size());
+    }
+  }
+  if (st == TMF_OK) {
+    if (prec == TMF_F64) {
+      InstDesc<double> d = make_desc<double>(op, 0);
+      st = op->desc.upload(&d, sizeof(d));
+    } else {
+      InstDesc<float> d = make_desc<float>(op, 0);
+      st = op->desc.upload(&d, sizeof(d));
     }
   }
   if (st == TMF_OK) {
@@ -586,7 +543,7 @@ GroupArgs group_args(const tmf_op *op) {
 
 template <typename T>
 hipError_t apply_t(tmf_op *op, const void *coeff, const void *x, void *y, hipStream_t s,
-                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool interface = true) {
   hipError_t e;
   T *yy = static_cast<T *>(y);
   if (op->space == 1) {
@@ -603,11 +560,10 @@ hipError_t apply_t(tmf_op *op, const void *coeff, const void *x, void *y, hipStr
     e = launch_fill<T>(yy, op->ncomp * op->n_local, T(0), s);
     if (e != hipSuccess) return e;
     TileArgs<T> a;
-    a.lat = lattice_args<T>(op);
+    a.inst = reinterpret_cast<const InstDesc<T> *>(op->desc.p);
     a.tiles = op->tiles[op->tile_cfg].p;
     a.ntiles = op->ntiles[op->tile_cfg];
-    a.n_local = op->n_local;
-    a.mgeo = reinterpret_cast<const MacroGeo<T> *>(op->mgeo.p);
+    a.active = nullptr;
     a.qtab = reinterpret_cast<const T *>(op->qtab.p);
     a.nq = op->nq;
     a.k = static_cast<const T *>(coeff);
@@ -617,7 +573,7 @@ hipError_t apply_t(tmf_op *op, const void *coeff, const void *x, void *y, hipStr
     e = launch_tile_apply<T>(a, op->kind, op->mesh->map, op->tile_cfg, s);
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
   }
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !interface) return e;
   return launch_interface_sum<T>(group_args(op), yy, s);
 }
 
@@ -631,12 +587,7 @@ hipError_t adjoint_t(tmf_op *op, const void *coeff, const void *x, const void *g
   a.gy = static_cast<const T *>(gy);
   a.gx = static_cast<T *>(gx);
   a.gk = static_cast<T *>(gk);
-  hipError_t e = launch_p1_adjoint<T>(a, s);
-  if (e != hipSuccess) return e;
-  GroupArgs g = group_args(op);
-  e = launch_interface_sum<T>(g, a.gx, s);
-  if (e != hipSuccess || !gk) return e;
-  return launch_interface_sum<T>(g, a.gk, s);
+  return launch_p1_adjoint<T>(a, s);
 }
 
 }  // namespace
@@ -667,6 +618,25 @@ tmf_status tmf_apply_timed(tmf_op *op, const void *coeff, const void *x, void *y
 
 tmf_status tmf_apply(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream) {
   return tmf_apply_timed(op, coeff, x, y, stream, nullptr, nullptr);
+}
+
+tmf_status tmf_apply_local(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream) {
+  tmf_status st = check_apply(op, coeff, x, y);
+  if (st != TMF_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = op->prec == TMF_F64 ? apply_t<double>(op, coeff, x, y, s, nullptr, nullptr, false)
+                                     : apply_t<float>(op, coeff, x, y, s, nullptr, nullptr, false);
+  if (e != hipSuccess) return hip_fail(e, "apply launch");
+  return TMF_OK;
+}
+
+tmf_status tmf_interface_sum(tmf_op *op, void *v, tmf_stream stream) {
+  if (!op || !v) return fail(TMF_EINVAL, "op or v is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = op->prec == TMF_F64 ? launch_interface_sum<double>(group_args(op), static_cast<double *>(v), s)
+                                     : launch_interface_sum<float>(group_args(op), static_cast<float *>(v), s);
+  if (e != hipSuccess) return hip_fail(e, "interface sum launch");
+  return TMF_OK;
 }
 
 static int num_tiles(const tmf_op *op) {

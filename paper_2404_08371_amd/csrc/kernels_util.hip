@@ -5,10 +5,23 @@ namespace tmf {
 
 namespace {
 
+// 16-byte stores over the 16-byte-aligned body, scalar stores for the ends
 template <typename T>
 __global__ __launch_bounds__(256) void k_fill(T *p, int64_t n, T v) {
+  constexpr int W = 16 / sizeof(T);
+  const int64_t head = ((16 - (reinterpret_cast<uintptr_t>(p) & 15)) & 15) / sizeof(T);
+  const int64_t h = head < n ? head : n;
+  const int64_t nv = (n - h) / W;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
-  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = v;
+  const int64_t tid = blockIdx.x * 256LL + threadIdx.x;
+  typedef T V __attribute__((ext_vector_type(W)));
+  V vv;
+  for (int q = 0; q < W; ++q) vv[q] = v;
+  V *pv = reinterpret_cast<V *>(p + h);
+  for (int64_t i = tid; i < nv; i += stride) pv[i] = vv;
+  if (tid < h) p[tid] = v;
+  const int64_t tail = h + nv * W;
+  if (tid < n - tail) p[tail + tid] = v;
 }
 
 // A DoF on a face, edge or vertex shared by several macro-tets has one copy
@@ -33,8 +46,9 @@ __global__ __launch_bounds__(256) void k_interface(GroupArgs g, T *y) {
 template <typename T>
 hipError_t launch_fill(T *p, int64_t n, T v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
+  int64_t blocks = (n / (16 / sizeof(T)) + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL((k_fill<T>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }

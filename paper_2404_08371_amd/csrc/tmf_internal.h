@@ -113,14 +113,27 @@ struct P1AdjArgs {
   T *gk;
 };
 
+// One operator instance as seen by the element kernels (a batch holds many).
+template <typename T>
+struct InstDesc {
+  int n, N, L, dirichlet;       // cubes per macro edge, P2 lattice size, points per macro, BC
+  int64_t off;                  // offset of the instance in the concatenated vectors
+  int64_t n_local;              // component stride of the instance's vector fields
+  const uint32_t *bnd;          // per macro boundary table
+  const TypeGeo<T> *geo;        // per macro x 6 types
+  const MacroGeo<T> *mgeo;      // per macro (curved maps)
+};
+
+// tile = (instance, macro, bx0 | by0 << 10 | bz0 << 20, 0) in micro-cube units
+__host__ __device__ inline int pack_base(int bx, int by, int bz) { return bx | (by << 10) | (bz << 20); }
+
 template <typename T>
 struct TileArgs {
-  LatticeArgs<T> lat;
-  const int4 *tiles;  // (macro, bx0, by0, bz0) in micro-cube units
+  const InstDesc<T> *inst;
+  const int4 *tiles;
   int ntiles;
-  int64_t n_local;    // component stride of vector fields
-  const MacroGeo<T> *mgeo;
-  const T *qtab;      // blended map: per quadrature point [w, bary(4), phi(10), refgrad(30)]
+  const uint8_t *active;  // per instance, NULL = all active; tiles of inactive instances are skipped
+  const T *qtab;          // blended map: per quadrature point [w, bary(4), phi(10), refgrad(30)]
   int nq;
   const T *k;
   const T *x;

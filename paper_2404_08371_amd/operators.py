@@ -128,8 +128,26 @@ class Operator:
             check(lib().tmf_apply(self._h, pk, px, py, _stream_handle(x.device)))
         return out
 
+    def apply_local(self, x, coeff=None, out=None):
+        """Macro-local partial sums (the apply without the interface sum)."""
+        px = self._vec(x, "x", self.ncomp)
+        pk = self._vec(coeff, "coeff", 1) if self.has_coeff else None
+        if out is None:
+            out = torch.empty_like(x)
+        py = self._vec(out, "out", self.ncomp)
+        with torch.cuda.device(x.device):
+            check(lib().tmf_apply_local(self._h, pk, px, py, _stream_handle(x.device)))
+        return out
+
+    def interface_sum_(self, v):
+        """In place: every copy of a shared DoF gets the sum over its copies."""
+        pv = self._vec(v, "v", self.ncomp)
+        with torch.cuda.device(v.device):
+            check(lib().tmf_interface_sum(self._h, pv, _stream_handle(v.device)))
+        return v
+
     def adjoint(self, coeff, x, gy, gx=None, gk=None, want_gk=True):
-        """Reverse mode of y = A(k) x (P1 div(k grad)): returns (gx, gk)."""
+        """Reverse mode of the macro-local apply of P1 div(k grad): returns (gx, gk)."""
         pk, px, pg = self._vec(coeff, "coeff", 1), self._vec(x, "x", 1), self._vec(gy, "gy", 1)
         if gx is None:
             gx = torch.empty_like(x)

@@ -73,3 +73,21 @@ def test_fp32_parity(mesh, level, kind):
     e2, ei = run_case(mesh, level, kind, O.BC_DIRICHLET_ZERO, T.F32)
     print("fp32 rel err", e2, ei)
     assert ei <= 2e-5, (e2, ei)
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("kind,prec", [(O.P2_DIVKGRAD, T.F64), (O.P2_LAPLACE, T.F64), (O.P2_DIVKGRAD, T.F32)])
+def test_every_tile_shape(cfg, kind, prec):
+    """Each autotuner candidate computes the same operator (level 4: 16 cubes per edge, ragged boxes)."""
+    import ctypes
+    print("tile case", cfg, kind, prec, flush=True)
+    m, op = lib_problem("cube", 4, kind, O.BC_DIRICHLET_ZERO, prec)
+    T.check(T.lib().tmf_op_set_tile(op.handle, cfg))
+    info = m.dof_info(2, owner=False, boundary=False)
+    x, k = inputs(kind, info["keys"], info["xyz"], 3)
+    pr = oracle_problem("cube", 4, kind, O.BC_DIRICHLET_ZERO)
+    dt = torch.float64 if prec == T.F64 else torch.float32
+    y = op.apply(torch.tensor(x, dtype=dt, device="cuda"),
+                 torch.tensor(k, dtype=dt, device="cuda") if k is not None else None)
+    e2, ei = rel_err(y.double().cpu().numpy(), pr.apply(x, k))
+    assert ei <= (1e-12 if prec == T.F64 else 2e-5), (e2, ei)
