@@ -154,6 +154,55 @@ def traffic_for(kernel_key):
     return ent["bytes_per_launch"]
 
 
+def batched_solve(torch, T, W, hip, steps):
+    """Batched P2 div(k grad): FP32 / FP64 batched applies and the refined solve to 1e-10."""
+    levels = W.fields.batch_levels()
+    a, phi = W.fields.batch_k_params()
+    v, t = W.meshes.ref_tet()
+    meshes = [T.Mesh(v, t, int(lv)) for lv in levels]
+    infos = [mm.dof_info(2, owner=False) for mm in meshes]
+    ops64 = [T.Operator(mm, T.P2_DIVKGRAD, T.F64) for mm in meshes]
+    ops32 = [T.Operator(mm, T.P2_DIVKGRAD, T.F32) for mm in meshes]
+    b64, b32 = T.Batch(ops64), T.Batch(ops32)
+    K = b64.concat([torch.tensor(W.fields.batch_k(inf["xyz"], a[i], phi[i]), device="cuda")
+                    for i, inf in enumerate(infos)])
+    Xs = b64.concat([torch.tensor(W.uniform_from_keys(11, inf["keys"]) * (~inf["boundary"]), device="cuda")
+                     for inf in infos])
+    B = b64.apply(Xs, K)
+    dofs = sum(op.n_unique for op in ops64)
+    res = {"instances": len(levels), "levels": [int(lv) for lv in levels], "dofs": dofs}
+    L = T.lib()
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for name, b, kk, xx in (("fp64", b64, K, Xs), ("fp32", b32, K.float(), Xs.float())):
+        yy = torch.empty_like(xx)
+        cfg, ms = b.autotune(xx, kk, yy, reps=3)
+        evs = [(hip.event(), hip.event()) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for e0, e1 in evs:
+            T.check(L.tmf_batch_apply_timed(b.handle, ctypes.c_void_p(kk.data_ptr()), ctypes.c_void_p(xx.data_ptr()),
+                                            ctypes.c_void_p(yy.data_ptr()), None, st, e0, e1))
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / steps
+        kern = float(np.mean([hip.elapsed_ms(e0, e1) for e0, e1 in evs]))
+        res["apply_%s_mdofs" % name] = round(dofs / (wall * 1e-3) / 1e6, 1)
+        res["apply_%s_kernel_ms" % name] = round(kern, 4)
+        res["apply_%s_tile" % name] = cfg
+    solver = T.IRSolver(b64, b32, tol=1e-10)
+    X = torch.zeros_like(B)
+    solver.solve(B, X, K, K.float())  # warm-up (graph capture)
+    X.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats, relres = solver.solve(B, X, K, K.float())
+    tsol = time.perf_counter() - t0
+    err = float(((X - Xs).norm() / Xs.norm()).item())
+    res.update({"solve_s": round(tsol, 4), "outer": stats["outer"], "inner_iterations": stats["inner_total"],
+                "graph_launches": stats["graph_launches"], "max_relres_fp64": float(relres.max()),
+                "rel_err_vs_exact": err, "converged": stats["converged"]})
+    return res
+
+
 def cpu_baseline_c2():
     """The oracle, as it stands, on one full apply of the headline workload (host cores)."""
     from threadpoolctl import threadpool_limits
@@ -299,6 +348,10 @@ def main():
             form("eps_blended_%s_shell_l6" % nm, ms6, oe, "eps", 4,
                  n_elements(24, 6) * 14 * FLOPS["eps_blended_per_q"], 7 * bpd * oe.n_local, pk, 5)
             del oe
+        # batched mixed-precision solve: 32 reference-tet instances, levels in {3..7}
+        log("batched FP32-in-FP64 refinement, 32 instances")
+        forms["batched_ir_cg_p2_divkgrad_32x"] = batched_solve(torch, T, W, hip, args.form_steps)
+        log("batched_ir_cg_p2_divkgrad_32x", forms["batched_ir_cg_p2_divkgrad_32x"])
         out["forms"] = forms
 
     if not args.no_cpu_baseline:

@@ -56,8 +56,6 @@ class Problem:
         self.ncomp = 3 if kind == P2V_EPSILON else 1
         self.qbary = None if qbary is None else np.asarray(qbary, dtype=np.float64)
         self.qw = None if qw is None else np.asarray(qw, dtype=np.float64)
-        if map_ == MAP_SHELL_RADIAL and (kind != P2V_EPSILON or self.qbary is None):
-            raise ValueError("the blended map is defined for the epsilon operator with a rule")
         self.pts = lattice_points(self.N)
         self._layout()
 
@@ -118,6 +116,8 @@ class Problem:
 
     def element_matrices(self, P, c_e, macro):
         k = self.kind
+        if self.map == MAP_SHELL_RADIAL and k != P2V_EPSILON:
+            raise ValueError("the blended map is defined for the epsilon operator")
         if k == P1_LAPLACE:
             return el.p1_laplace(P)
         if k == P1_DIVKGRAD:
@@ -128,6 +128,8 @@ class Problem:
             return el.p2_divkgrad(P, c_e)
         if self.map == MAP_AFFINE:
             return el.eps_affine(P, c_e)
+        if self.qbary is None:
+            raise ValueError("the blended map needs a quadrature rule")
         s = np.sign(self.V[self.tets[macro]].mean(0))
         return el.eps_blended(P, c_e, s, self.qbary, self.qw)
 
