@@ -7,7 +7,7 @@
 //      coefficient, Dirichlet mask applied to x) from HBM into LDS,
 //   2. applies the fused local operator to every micro-tet of the box -- one
 //      lane per micro-tet, one type per wavefront -- and accumulates the 10
-//      (or 30) local results into an LDS copy of y,
+//      (or 30) local results into an FP64 LDS copy of y,
 //   3. writes y: points touched only by this box are stored directly; points
 //      on the box faces shared with neighbouring boxes are added into y
 //      (zero-filled beforehand) with hardware FP atomics.
@@ -294,35 +294,6 @@ __device__ inline void eps_blended_elem(const T u[3][10], const T mu[10], const 
   }
 }
 
-// Cubes of a TX x TY x TZ box sorted by cx + cy + cz.  A box clipped by the
-// diagonal face of the macro keeps, for each micro-tet type, exactly a prefix
-// of this order (type t exists iff the cube's index sum is <= n - kLim[t]),
-// so the valid elements of every type are enumerated without gaps.
-template <int TX, int TY, int TZ>
-struct CubeOrder {
-  static constexpr int C = TX * TY * TZ;
-  static constexpr int S = TX + TY + TZ - 2;  // distinct sums 0..S-1
-  int packed[C];                              // cx | cy << 8 | cz << 16
-  int cnt[S];                                 // cubes with sum <= s
-};
-
-template <int TX, int TY, int TZ>
-constexpr CubeOrder<TX, TY, TZ> make_order() {
-  CubeOrder<TX, TY, TZ> o{};
-  int q = 0;
-  for (int s = 0; s < o.S; ++s) {
-    for (int cz = 0; cz < TZ; ++cz)
-      for (int cy = 0; cy < TY; ++cy)
-        for (int cx = 0; cx < TX; ++cx)
-          if (cx + cy + cz == s) o.packed[q++] = cx | (cy << 8) | (cz << 16);
-    o.cnt[s] = q;
-  }
-  return o;
-}
-
-template <int TX, int TY, int TZ>
-__constant__ CubeOrder<TX, TY, TZ> kOrder = make_order<TX, TY, TZ>();
-
 template <typename T, int KIND, int MAP, int TX, int TY, int TZ>
 struct TileCfg {
   static constexpr int RX = 2 * TX + 1, RY = 2 * TY + 1, RZ = 2 * TZ + 1;
@@ -330,40 +301,26 @@ struct TileCfg {
   static constexpr int C = TX * TY * TZ;
   static constexpr int NC = KIND == P2V_EPSILON ? 3 : 1;
   static constexpr bool HASK = KIND != P2_LAPLACE;
-  static constexpr int NTH = (6 * C) < 768 ? 6 * C : 768;
+  // 4 waves per workgroup: with the FP64 element code (~96 VGPRs) this keeps
+  // four workgroups resident per CU, where 12-wave groups fit only one
+  static constexpr int NTH = 256;
+  static_assert(C % 64 == 0, "one micro-tet type per wavefront needs 64 | cubes per tile");
 };
 
-// LDS offset (in elements) of local node v of type t from the cube's base node
-template <int RX, int RY, int t, int v>
-constexpr int node_off() {
-  int o[3] = {0, 0, 0};
-  for (int d = 0; d < 3; ++d)
-    o[d] = v < 4 ? 2 * kOff[t][v][d] : kOff[t][kEdge[v - 4][0]][d] + kOff[t][kEdge[v - 4][1]][d];
-  return o[0] + RX * (o[1] + RY * o[2]);
-}
-
-template <int RX, int RY, int t>
-struct NodeOffsets {
-  static constexpr int v[10] = {node_off<RX, RY, t, 0>(), node_off<RX, RY, t, 1>(), node_off<RX, RY, t, 2>(),
-                                node_off<RX, RY, t, 3>(), node_off<RX, RY, t, 4>(), node_off<RX, RY, t, 5>(),
-                                node_off<RX, RY, t, 6>(), node_off<RX, RY, t, 7>(), node_off<RX, RY, t, 8>(),
-                                node_off<RX, RY, t, 9>()};
-};
-
-// one micro-tet of type t whose cube starts at LDS node cb
-template <typename T, int KIND, int MAP, int RX, int RY, int R, int t>
+// one micro-tet whose 10 local nodes sit at LDS points li[]
+template <typename T, int KIND, int MAP, int R>
 __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T> *D, T (*sx)[R], const T *sk,
-                                          T (*sy)[R], int cb, int m, int bxc, int byc, int bzc) {
-  using O = NodeOffsets<RX, RY, t>;
+                                          double (*sy)[R], const int li[10], int t, int m, int bxc, int byc,
+                                          int bzc) {
   const TypeGeo<T> *g = D->geo + 6 * m + t;
   if constexpr (KIND == P2V_EPSILON) {
     T u[3][10], mu[10], y[3][10];
 #pragma unroll
     for (int v = 0; v < 10; ++v) {
-      u[0][v] = sx[0][cb + O::v[v]];
-      u[1][v] = sx[1][cb + O::v[v]];
-      u[2][v] = sx[2][cb + O::v[v]];
-      mu[v] = sk[cb + O::v[v]];
+      u[0][v] = sx[0][li[v]];
+      u[1][v] = sx[1][li[v]];
+      u[2][v] = sx[2][li[v]];
+      mu[v] = sk[li[v]];
     }
     if constexpr (MAP == 0) {
       eps_elem(u, mu, g->grad, g->vol, y);
@@ -380,178 +337,119 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
 #pragma unroll
     for (int v = 0; v < 10; ++v)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) atomicAdd(&sy[c][cb + O::v[v]], y[c][v]);
+      for (int c = 0; c < 3; ++c) atomicAdd(&sy[c][li[v]], double(y[c][v]));
   } else {
     constexpr bool HASK = KIND != P2_LAPLACE;
     T u[10], kv[10], y[10];
 #pragma unroll
     for (int v = 0; v < 10; ++v) {
-      u[v] = sx[0][cb + O::v[v]];
-      kv[v] = HASK ? sk[cb + O::v[v]] : T(1);
+      u[v] = sx[0][li[v]];
+      kv[v] = HASK ? sk[li[v]] : T(1);
     }
     p2_elem<T, HASK>(u, kv, g->Gp, y);
 #pragma unroll
-    for (int v = 0; v < 10; ++v) atomicAdd(&sy[0][cb + O::v[v]], y[v]);
+    for (int v = 0; v < 10; ++v) atomicAdd(&sy[0][li[v]], double(y[v]));
   }
 }
 
-// Persistent element kernel.  Each workgroup walks a contiguous chunk of the
-// tile list (one chunk per XCD: consecutive workgroup ids are dispatched
-// round-robin over the XCDs, so the tiles of one chunk -- spatial neighbours
-// that share halo inputs and seam outputs -- stay in one L2).  While the
-// micro-tets of tile i are computed from LDS, the global loads of tile i+1
-// are already in flight into registers.
+// One workgroup per tile.  Workgroup ids are dispatched round-robin over the
+// 8 XCDs; the id -> tile map below is a bijection that gives every XCD a
+// contiguous run of the (spatially ordered) tile list, so neighbouring boxes
+// -- which share halo inputs and seam outputs -- meet in the same L2.
 template <typename T, int KIND, int MAP, int TX, int TY, int TZ>
 __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_tile(TileArgs<T> a) {
   using Cfg = TileCfg<T, KIND, MAP, TX, TY, TZ>;
   constexpr int RX = Cfg::RX, RY = Cfg::RY, R = Cfg::R, NC = Cfg::NC, NTH = Cfg::NTH;
   constexpr bool HASK = Cfg::HASK;
-  constexpr int NJ = (R + NTH - 1) / NTH;  // region points per thread
   __shared__ T sx[NC][R];
-  __shared__ T sy[NC][R];
+  // the element results are accumulated in FP64 in both precisions: FP64
+  // LDS atomics run at full speed on gfx950 where FP32 ones stall the LDS
+  // pipeline, and the partial sums of a point keep 53-bit mantissas
+  __shared__ double sy[NC][R];
   __shared__ T sk[HASK ? R : 1];
+  __shared__ int snoff[6][10];
 
   const int tid = threadIdx.x;
-  const int nxcd = gridDim.x < 8 ? gridDim.x : 8;
-  const int xcd = blockIdx.x % nxcd;
-  const int wg_here = (gridDim.x - xcd + nxcd - 1) / nxcd;
-  const int per = (a.ntiles + nxcd - 1) / nxcd;
-  const int t_end = min(a.ntiles, (xcd + 1) * per);
-  int ti = xcd * per + blockIdx.x / nxcd;
-  if (ti >= t_end) return;
+  const int nxcd = 8;
+  const int q = a.ntiles / nxcd, rem = a.ntiles % nxcd;
+  const int x8 = blockIdx.x % nxcd;
+  const int ti = x8 * q + (x8 < rem ? x8 : rem) + static_cast<int>(blockIdx.x) / nxcd;
+  const int4 tl = a.tiles[ti];
+  const InstDesc<T> *D = a.inst + tl.x;
+  if (a.active != nullptr && a.active[tl.x] == 0) return;
+  const int m = tl.y;
+  const int bx0 = tl.z & 1023, by0 = (tl.z >> 10) & 1023, bz0 = (tl.z >> 20) & 1023;
+  const int N = D->N, n = D->n;
+  const int64_t nl = D->n_local;
+  const uint32_t bnd = D->dirichlet ? D->bnd[m] : 0u;
+  const int64_t base = D->off + static_cast<int64_t>(m) * D->L;
 
-  // prefetched state of the next tile
-  int nm, nb[3], ninst;
-  T px[NJ][NC], pk[NJ];
-  int64_t pgi[NJ];
-  int pfl[NJ];  // bit0 in mesh, bit1 Dirichlet DoF, bit2 touched only by this box
-  auto prefetch = [&](int id) {
-    const int4 tl = a.tiles[id];
-    ninst = tl.x;
-    nm = tl.y;
-    nb[0] = tl.z & 1023;
-    nb[1] = (tl.z >> 10) & 1023;
-    nb[2] = (tl.z >> 20) & 1023;
-    const InstDesc<T> &D = a.inst[ninst];
-    const int N = D.N;
-    const bool act = a.active == nullptr || a.active[ninst] != 0;
-    const uint32_t bnd = D.dirichlet ? D.bnd[nm] : 0u;
-    const int64_t base = D.off + static_cast<int64_t>(nm) * D.L;
+  if (tid < 60) {
+    const int t = tid / 10, v = tid % 10;
+    int o[3];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int r = tid + j * NTH;
-      const int rx = r % RX, ry = (r / RX) % RY, rz = r / (RX * RY);
-      const int qi = 2 * nb[0] + rx, qj = 2 * nb[1] + ry, qk = 2 * nb[2] + rz;
-      int fl = 0;
+    for (int d = 0; d < 3; ++d)
+      o[d] = v < 4 ? 2 * kOff[t][v][d] : kOff[t][kEdge[v - 4][0]][d] + kOff[t][kEdge[v - 4][1]][d];
+    snoff[t][v] = o[0] + RX * (o[1] + RY * o[2]);
+  }
+  // 1. stage the box: x with Dirichlet DoFs zeroed, and the coefficient
+  for (int r = tid; r < R; r += NTH) {
+    const int rx = r % RX, ry = (r / RX) % RY, rz = r / (RX * RY);
+    const int qi = 2 * bx0 + rx, qj = 2 * by0 + ry, qk = 2 * bz0 + rz;
+    T xv[NC], kv = T(0);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) px[j][c] = T(0);
-      pk[j] = T(0);
-      pgi[j] = 0;
-      if (act && r < R && qi + qj + qk <= N) {
-        const int64_t gi = base + row_base(qj, qk, N) + qi;
-        const bool masked = (bnd >> zero_pattern(qi, qj, qk, N)) & 1u;
-        const bool excl = ((rx & 1) || ((rx > 0 || nb[0] == 0) && rx < 2 * TX)) &&
-                          ((ry & 1) || ((ry > 0 || nb[1] == 0) && ry < 2 * TY)) &&
-                          ((rz & 1) || ((rz > 0 || nb[2] == 0) && rz < 2 * TZ));
-        fl = 1 | (int(masked) << 1) | (int(excl) << 2);
-        pgi[j] = gi;
-        if (!masked) {
+    for (int c = 0; c < NC; ++c) xv[c] = T(0);
+    if (qi + qj + qk <= N) {
+      const int64_t gi = base + row_base(qj, qk, N) + qi;
+      if (!((bnd >> zero_pattern(qi, qj, qk, N)) & 1u)) {
 #pragma unroll
-          for (int c = 0; c < NC; ++c) px[j][c] = a.x[gi + c * D.n_local];
-        }
-        if (HASK) pk[j] = a.k[gi];
+        for (int c = 0; c < NC; ++c) xv[c] = a.x[gi + c * nl];
       }
-      pfl[j] = fl;
+      if (HASK) kv = a.k[gi];
     }
-  };
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      sx[c][r] = xv[c];
+      sy[c][r] = 0.0;
+    }
+    if (HASK) sk[r] = kv;
+  }
+  __syncthreads();
 
-  prefetch(ti);
-  for (;;) {
-    // current tile <- prefetched tile
-    const int m = nm, bx0 = nb[0], by0 = nb[1], bz0 = nb[2];
-    const InstDesc<T> *D = a.inst + ninst;
-    const int n = D->n;
-    const int64_t nl = D->n_local;
-    const bool act = a.active == nullptr || a.active[ninst] != 0;
-    int64_t cgi[NJ];
-    int cfl[NJ];
+  // 2. micro-tets: slot e -> (type e / C, cube e % C, x fastest); C is a
+  // multiple of 64, so the type is wave-uniform
+  constexpr int C = Cfg::C;
+  const int s0 = bx0 + by0 + bz0;
+  for (int e = tid; e < 6 * C; e += NTH) {
+    const int t = __builtin_amdgcn_readfirstlane(e / C);
+    const int c = e - t * C;
+    const int cx = c % TX, cy = (c / TX) % TY, cz = c / (TX * TY);
+    if (s0 + cx + cy + cz > n - kLim[t]) continue;
+    const int cb = 2 * cx + RX * (2 * cy + RY * 2 * cz);
+    int li[10];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int r = tid + j * NTH;
-      cgi[j] = pgi[j];
-      cfl[j] = pfl[j];
-      if (r < R) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          sx[c][r] = px[j][c];
-          sy[c][r] = T(0);
-        }
-        if (HASK) sk[r] = pk[j];
-      }
-    }
-    __syncthreads();
-    const int tn = ti + wg_here;
-    if (tn < t_end) prefetch(tn);
+    for (int v = 0; v < 10; ++v) li[v] = cb + snoff[t][v];
+    tile_elem<T, KIND, MAP, R>(a, D, sx, sk, sy, li, t, m, bx0 + cx, by0 + cy, bz0 + cz);
+  }
+  __syncthreads();
 
-    // micro-tets: work units of 64 valid cubes of one type
-    const int s0 = bx0 + by0 + bz0;
-    int cnt[6], pre[7];
-    pre[0] = 0;
+  // 3. write back: points touched only by this box are stored, shared face points added
+  for (int r = tid; r < R; r += NTH) {
+    const int rx = r % RX, ry = (r / RX) % RY, rz = r / (RX * RY);
+    const int qi = 2 * bx0 + rx, qj = 2 * by0 + ry, qk = 2 * bz0 + rz;
+    if (qi + qj + qk > N) continue;
+    if ((bnd >> zero_pattern(qi, qj, qk, N)) & 1u) continue;
+    const bool excl = ((rx & 1) || ((rx > 0 || bx0 == 0) && rx < 2 * TX)) &&
+                      ((ry & 1) || ((ry > 0 || by0 == 0) && ry < 2 * TY)) &&
+                      ((rz & 1) || ((rz > 0 || bz0 == 0) && rz < 2 * TZ));
+    const int64_t gi = base + row_base(qj, qk, N) + qi;
 #pragma unroll
-    for (int t = 0; t < 6; ++t) {
-      const int smax = n - kLim[t] - s0;
-      cnt[t] = (!act || smax < 0) ? 0 : kOrder<TX, TY, TZ>.cnt[smax >= TX + TY + TZ - 2 ? TX + TY + TZ - 3 : smax];
-      pre[t + 1] = pre[t] + (cnt[t] + 63) / 64;
+    for (int c = 0; c < NC; ++c) {
+      if (excl)
+        a.y[gi + c * nl] = T(sy[c][r]);
+      else
+        atomicAdd(a.y + gi + c * nl, T(sy[c][r]));
     }
-    const int lane = tid & 63;
-    const bool full = s0 + TX + TY + TZ - 3 <= n - 3;
-    for (int u = tid >> 6; u < pre[6]; u += NTH / 64) {
-      int t = 0;
-#pragma unroll
-      for (int q = 1; q < 6; ++q) t += (u >= pre[q]) ? 1 : 0;
-      t = __builtin_amdgcn_readfirstlane(t);
-      const int rank = (u - pre[t]) * 64 + lane;
-      if (rank >= cnt[t]) continue;
-      int cx, cy, cz;
-      if (full) {
-        cx = rank % TX;
-        cy = (rank / TX) % TY;
-        cz = rank / (TX * TY);
-      } else {
-        const int pkd = kOrder<TX, TY, TZ>.packed[rank];
-        cx = pkd & 255;
-        cy = (pkd >> 8) & 255;
-        cz = pkd >> 16;
-      }
-      const int cb = 2 * cx + RX * (2 * cy + RY * 2 * cz);
-      const int bxc = bx0 + cx, byc = by0 + cy, bzc = bz0 + cz;
-      switch (t) {
-        case 0: tile_elem<T, KIND, MAP, RX, RY, R, 0>(a, D, sx, sk, sy, cb, m, bxc, byc, bzc); break;
-        case 1: tile_elem<T, KIND, MAP, RX, RY, R, 1>(a, D, sx, sk, sy, cb, m, bxc, byc, bzc); break;
-        case 2: tile_elem<T, KIND, MAP, RX, RY, R, 2>(a, D, sx, sk, sy, cb, m, bxc, byc, bzc); break;
-        case 3: tile_elem<T, KIND, MAP, RX, RY, R, 3>(a, D, sx, sk, sy, cb, m, bxc, byc, bzc); break;
-        case 4: tile_elem<T, KIND, MAP, RX, RY, R, 4>(a, D, sx, sk, sy, cb, m, bxc, byc, bzc); break;
-        default: tile_elem<T, KIND, MAP, RX, RY, R, 5>(a, D, sx, sk, sy, cb, m, bxc, byc, bzc); break;
-      }
-    }
-    __syncthreads();
-
-    // write back: points touched only by this box are stored, shared face points added
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int r = tid + j * NTH;
-      if ((cfl[j] & 3) != 1) continue;
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        if (cfl[j] & 4)
-          a.y[cgi[j] + c * nl] = sy[c][r];
-        else
-          atomicAdd(a.y + cgi[j] + c * nl, sy[c][r]);
-      }
-    }
-    if (tn >= t_end) break;
-    ti = tn;
-    __syncthreads();
   }
 }
 
@@ -559,19 +457,7 @@ template <typename T, int KIND, int MAP, int TX, int TY, int TZ>
 hipError_t launch_cfg(const TileArgs<T> &a, hipStream_t s) {
   using Cfg = TileCfg<T, KIND, MAP, TX, TY, TZ>;
   if (a.ntiles == 0) return hipSuccess;
-  // persistent grid: as many workgroups as fit on the device at once
-  static int grid = 0;
-  if (grid == 0) {
-    int dev = 0, cus = 0, per_cu = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile<T, KIND, MAP, TX, TY, TZ>, Cfg::NTH, 0);
-    if (e != hipSuccess) return e;
-    grid = cus * (per_cu > 0 ? per_cu : 1);
-  }
-  const int g = a.ntiles < grid ? a.ntiles : grid;
-  hipLaunchKernelGGL((k_tile<T, KIND, MAP, TX, TY, TZ>), dim3(g), dim3(Cfg::NTH), 0, s, a);
+  hipLaunchKernelGGL((k_tile<T, KIND, MAP, TX, TY, TZ>), dim3(a.ntiles), dim3(Cfg::NTH), 0, s, a);
   return hipGetLastError();
 }
 
