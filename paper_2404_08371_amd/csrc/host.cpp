@@ -305,7 +305,7 @@ template <typename T>
 void fill_geometry(const tmf_mesh *m, std::vector<TypeGeo<T>> &geo, std::vector<T> &w15,
                    std::vector<MacroGeo<T>> &mg) {
   geo.assign(6 * m->nt, TypeGeo<T>{});
-  w15.assign(15 * m->nt, T(0));
+  w15.assign(16 * 15 * m->nt, T(0));
   mg.assign(m->nt, MacroGeo<T>{});
   for (int64_t mac = 0; mac < m->nt; ++mac) {
     const int64_t *g = &m->T[4 * mac];
@@ -317,7 +317,7 @@ void fill_geometry(const tmf_mesh *m, std::vector<TypeGeo<T>> &geo, std::vector<
       mg[mac].s[d] = T(m->sgn[3 * mac + d]);
     }
     for (int q = 0; q < 9; ++q) mg[mac].JM[q] = T(JM[q]);
-    double w[15] = {0};
+    double w[16][15] = {{0}};
     for (int t = 0; t < 6; ++t) {
       double E[9], J[9], Ji[9], det;
       for (int d = 0; d < 3; ++d)
@@ -347,11 +347,21 @@ void fill_geometry(const tmf_mesh *m, std::vector<TypeGeo<T>> &geo, std::vector<
         for (int d = 0; d < 3; ++d) tg.grad[3 * a + d] = T(gr[a][d]);
       tg.vol = T(vol);
       for (int q = 0; q < 9; ++q) tg.JT[q] = T(J[q]);
-      for (int a = 0; a < 4; ++a)
-        for (int c = 0; c < 4; ++c)
-          w[vslot(t, a, c)] += vol * (gr[a][0] * gr[c][0] + gr[a][1] * gr[c][1] + gr[a][2] * gr[c][2]);
+      // 15-point stencils per boundary class z (zero pattern of the point):
+      // micro-tet (t, slot a) exists unless the point lies on a macro face the
+      // tet would have to cross
+      for (int a = 0; a < 4; ++a) {
+        const int ox = kOff[t][a][0], oy = kOff[t][a][1], oz = kOff[t][a][2];
+        const int bad = (ox + oy + oz < kLim[t] ? 1 : 0) | (ox ? 2 : 0) | (oy ? 4 : 0) | (oz ? 8 : 0);
+        for (int z = 0; z < 16; ++z) {
+          if (z & bad) continue;
+          for (int c = 0; c < 4; ++c)
+            w[z][vslot(t, a, c)] += vol * (gr[a][0] * gr[c][0] + gr[a][1] * gr[c][1] + gr[a][2] * gr[c][2]);
+        }
+      }
     }
-    for (int q = 0; q < 15; ++q) w15[15 * mac + q] = T(w[q]);
+    for (int z = 0; z < 16; ++z)
+      for (int q = 0; q < 15; ++q) w15[(16 * mac + z) * 15 + q] = T(w[z][q]);
   }
 }
 
@@ -467,6 +477,16 @@ tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const
     }
   }
   if (st == TMF_OK) st = op->bnd.upload(mesh->bnd.data(), mesh->bnd.size());
+  if (st == TMF_OK && space == 1) {
+    // the rows of the packed lattice cut into chunks of at most 64 points
+    std::vector<int4> ch;
+    const int N = S.N;
+    for (int k = 0; k <= N; ++k)
+      for (int j = 0; j <= N - k; ++j)
+        for (int i0 = 0; i0 <= N - k - j; i0 += 64) ch.push_back(make_int4(j, k, i0, std::min(64, N - k - j - i0 + 1)));
+    op->nchunks = static_cast<int>(ch.size());
+    st = op->chunks.upload(ch.data(), ch.size());
+  }
   if (st == TMF_OK && space == 2) {
     const int n = mesh->n;
     for (int cfg = 0; cfg < kNumTileCfg && st == TMF_OK; ++cfg) {
@@ -554,7 +574,7 @@ hipError_t apply_t(tmf_op *op, const void *coeff, const void *x, void *y, hipStr
     a.x = static_cast<const T *>(x);
     a.y = yy;
     if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
-    e = launch_p1_apply<T>(a, op->kind, s);
+    e = launch_p1_apply<T>(a, op->kind, op->chunks.p, op->nchunks, s);
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
   } else {
     e = launch_fill<T>(yy, op->ncomp * op->n_local, T(0), s);
@@ -587,7 +607,7 @@ hipError_t adjoint_t(tmf_op *op, const void *coeff, const void *x, const void *g
   a.gy = static_cast<const T *>(gy);
   a.gx = static_cast<T *>(gx);
   a.gk = static_cast<T *>(gk);
-  return launch_p1_adjoint<T>(a, s);
+  return launch_p1_adjoint<T>(a, op->chunks.p, op->nchunks, s);
 }
 
 }  // namespace

@@ -1,19 +1,25 @@
 // P1 operators: vertex-centric ("owner computes") matrix-free kernels.
 //
-// Each thread owns one lattice point p of one macro and forms row p of
-// A x directly: y_p = sum over the (up to 24) micro-tets T containing p of
+// Each thread owns one lattice point p = (i, j, k) of one macro and forms row
+// p of A x: y_p = sum over the (up to 24) micro-tets T containing p of
 // (A_T x_T)_p (equation (4.1) restricted to one row).  Every row is written
-// exactly once, so there are no write conflicts, no atomics and the
-// summation order is fixed.  The 15-point neighbourhood of p is loaded once
-// into registers; the local matrices are the per-(macro, type) constants
-// Gp = |T| grad(lambda_a).grad(lambda_b) (affine macros: every micro-tet of a
-// type has the same Jacobian -- the loop-invariant hoisting of section
-// "Automatic Identification of Loop Invariants" done once on the host).
+// exactly once: no write conflicts, no atomics, fixed summation order.  A
+// wavefront owns a chunk of up to 64 consecutive points of one lattice row
+// (a host-built table lists the chunks, so no thread decodes a packed index),
+// the row bases of the 7 lattice rows its 15-point neighbourhoods touch are
+// computed once per wavefront, and all 15 neighbour loads of a point are
+// issued together (neighbouring lanes read neighbouring words).  Chunks at
+// distance >= 2 from every macro face (the bulk) take an unguarded path;
+// the others check each neighbour and zero Dirichlet DoFs of x (x_b ignored).
 //
-// Points at distance >= 2 from every macro face take a fast path: all 24
-// micro-tets exist and no neighbour is a Dirichlet DoF, so the constant
-// coefficient operator is a 15-point stencil.  Other points test each
-// candidate micro-tet and mask boundary neighbours.
+// The local matrices are the per-(macro, type) constants
+// Gp = |T| grad(lambda_a).grad(lambda_b) (affine macros: every micro-tet of
+// a type shares its Jacobian -- the loop-invariant hoisting of section
+// "Automatic Identification of Loop Invariants", done once on the host).
+// For the constant-coefficient operator they are pre-summed into 15-point
+// stencils, one per boundary class: which of the four macro faces (i = 0,
+// j = 0, k = 0, i + j + k = N) the point lies on decides which of its 24
+// micro-tets exist, so 16 stencils cover every point of a macro.
 #include "tmf_internal.h"
 
 namespace tmf {
@@ -32,211 +38,263 @@ constexpr VSlotTable make_vslot() {
 }
 constexpr VSlotTable kVS = make_vslot();
 
-// linear index within a macro lattice of size N -> (i, j, k)
-__device__ inline void decode(int r, int N, int &i, int &j, int &k) {
-  const int rem = c3(N) - r;  // >= 1: points in planes at or above the one holding r
-  int M = static_cast<int>(cbrtf(6.0f * static_cast<float>(rem))) - 2;
-  M = M < 0 ? 0 : (M > N ? N : M);
-  while (M < N && c3(M) < rem) ++M;
-  while (M > 0 && c3(M - 1) >= rem) --M;
-  k = N - M;
-  const int q = r - (c3(N) - c3(M));
-  const float B = 2.0f * M + 3.0f;
-  int jj = static_cast<int>(0.5f * (B - sqrtf(fmaxf(B * B - 8.0f * q, 0.0f))));
-  jj = jj < 0 ? 0 : (jj > M ? M : jj);
-  while (jj < M && ((jj + 1) * (2 * M + 3 - (jj + 1))) / 2 <= q) ++jj;
-  while (jj > 0 && (jj * (2 * M + 3 - jj)) / 2 > q) --jj;
-  j = jj;
-  i = q - (jj * (2 * M + 3 - jj)) / 2;
+// 15-point neighbour q -> (plane: 0 = k-1, 1 = k, 2 = k+1; in-plane slot)
+constexpr int kNbPlane[15] = {1, 1, 1, 1, 1, 2, 0, 1, 1, 0, 2, 0, 2, 2, 0};
+constexpr int kNbSlot[15] = {0, 1, 2, 3, 4, 0, 0, 5, 6, 1, 2, 3, 4, 5, 6};
+
+static_assert(kNb[5][2] == 1 && kNb[6][2] == -1 && kNb[13][0] == 1 && kNb[14][2] == -1, "neighbour table");
+
+// micro-tet (t, slot a) containing p exists, given p's zero pattern z
+// (bit 0: i+j+k = N, bit 1: i = 0, bit 2: j = 0, bit 3: k = 0)
+template <int t, int a>
+__device__ __forceinline__ bool tet_exists(int z) {
+  constexpr int ox = kOff[t][a][0], oy = kOff[t][a][1], oz = kOff[t][a][2];
+  constexpr bool diag = ox + oy + oz < kLim[t];
+  constexpr int bad = (diag ? 1 : 0) | (ox ? 2 : 0) | (oy ? 4 : 0) | (oz ? 8 : 0);
+  return (z & bad) == 0;
 }
 
-__device__ inline bool is_bnd(uint32_t bnd, int i, int j, int k, int N) {
-  return (bnd >> zero_pattern(i, j, k, N)) & 1u;
+template <typename T>
+__device__ __forceinline__ T nbval(const T P[3][7], int q) {
+  return P[kNbPlane[q]][kNbSlot[q]];
 }
 
-// load v at the 15-point neighbourhood; missing points read 0, and with MASK
-// Dirichlet-boundary points read 0 as well
-template <typename T, bool CHECK>
-__device__ inline void load15(const T *__restrict__ v, int i, int j, int k, int N, bool mask,
-                              uint32_t bnd, T out[15]) {
-#pragma unroll
-  for (int s = 0; s < 15; ++s) {
-    const int ii = i + kNb[s][0], jj = j + kNb[s][1], kk = k + kNb[s][2];
-    bool ok = true;
-    if (CHECK) {
-      ok = ii >= 0 && jj >= 0 && kk >= 0 && ii + jj + kk <= N;
-      if (ok && mask) ok = !is_bnd(bnd, ii, jj, kk, N);
-    }
-    T val = T(0);
-    if (ok) val = v[row_base(jj, kk, N) + ii];
-    out[s] = val;
-  }
+// row p of sum_T kbar_T Gp_T x_T over the existing micro-tets containing p
+template <typename T, int t, int a>
+__device__ __forceinline__ void p1k_tet(const TypeGeo<T> *__restrict__ g, const T X[3][7], const T K[3][7], int z,
+                                        T &acc) {
+  const T *G = g[t].Gp + 4 * a;
+  const int q0 = kVS.v[t][a][0], q1 = kVS.v[t][a][1], q2 = kVS.v[t][a][2], q3 = kVS.v[t][a][3];
+  const T r = G[0] * nbval(X, q0) + G[1] * nbval(X, q1) + G[2] * nbval(X, q2) + G[3] * nbval(X, q3);
+  const T kb = (nbval(K, q0) + nbval(K, q1) + nbval(K, q2) + nbval(K, q3)) * T(0.25);
+  const T c = kb * r;
+  acc += tet_exists<t, a>(z) ? c : T(0);
 }
 
-template <bool CHECK>
-__device__ inline bool tet_exists(int t, int a, int i, int j, int k, int N) {
-  if (!CHECK) return true;
-  const int bx = i - kOff[t][a][0], by = j - kOff[t][a][1], bz = k - kOff[t][a][2];
-  return bx >= 0 && by >= 0 && bz >= 0 && bx + by + bz <= N - kLim[t];
-}
-
-// row p of sum_T kbar_T Gp_T x_T over the micro-tets containing p
-template <typename T, bool VARK, bool CHECK>
-__device__ inline T p1_row(const TypeGeo<T> *__restrict__ g, const T xs[15], const T ks[15], int i,
-                           int j, int k, int N) {
+template <typename T>
+__device__ __forceinline__ T p1k_row(const TypeGeo<T> *g, const T X[3][7], const T K[3][7], int z) {
   T acc = T(0);
-#pragma unroll
-  for (int t = 0; t < 6; ++t) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      if (tet_exists<CHECK>(t, a, i, j, k, N)) {
-        const T *G = g[t].Gp + 4 * a;
-        T r = G[0] * xs[kVS.v[t][a][0]];
-        r += G[1] * xs[kVS.v[t][a][1]];
-        r += G[2] * xs[kVS.v[t][a][2]];
-        r += G[3] * xs[kVS.v[t][a][3]];
-        if (VARK) {
-          const T kb = (ks[kVS.v[t][a][0]] + ks[kVS.v[t][a][1]] + ks[kVS.v[t][a][2]] +
-                        ks[kVS.v[t][a][3]]) * T(0.25);
-          acc += kb * r;
-        } else {
-          acc += r;
-        }
-      }
-    }
-  }
+  p1k_tet<T, 0, 0>(g, X, K, z, acc); p1k_tet<T, 0, 1>(g, X, K, z, acc);
+  p1k_tet<T, 0, 2>(g, X, K, z, acc); p1k_tet<T, 0, 3>(g, X, K, z, acc);
+  p1k_tet<T, 1, 0>(g, X, K, z, acc); p1k_tet<T, 1, 1>(g, X, K, z, acc);
+  p1k_tet<T, 1, 2>(g, X, K, z, acc); p1k_tet<T, 1, 3>(g, X, K, z, acc);
+  p1k_tet<T, 2, 0>(g, X, K, z, acc); p1k_tet<T, 2, 1>(g, X, K, z, acc);
+  p1k_tet<T, 2, 2>(g, X, K, z, acc); p1k_tet<T, 2, 3>(g, X, K, z, acc);
+  p1k_tet<T, 3, 0>(g, X, K, z, acc); p1k_tet<T, 3, 1>(g, X, K, z, acc);
+  p1k_tet<T, 3, 2>(g, X, K, z, acc); p1k_tet<T, 3, 3>(g, X, K, z, acc);
+  p1k_tet<T, 4, 0>(g, X, K, z, acc); p1k_tet<T, 4, 1>(g, X, K, z, acc);
+  p1k_tet<T, 4, 2>(g, X, K, z, acc); p1k_tet<T, 4, 3>(g, X, K, z, acc);
+  p1k_tet<T, 5, 0>(g, X, K, z, acc); p1k_tet<T, 5, 1>(g, X, K, z, acc);
+  p1k_tet<T, 5, 2>(g, X, K, z, acc); p1k_tet<T, 5, 3>(g, X, K, z, acc);
   return acc;
 }
 
+// 1/4 (D gy)_T . Gp_T (D x)_T summed over the existing micro-tets containing p
+template <typename T, int t, int a>
+__device__ __forceinline__ void kgrad_tet(const TypeGeo<T> *__restrict__ g, const T R[3][7], const T X[3][7], int z,
+                                          T &acc) {
+  const T *G = g[t].Gp;
+  T bil = T(0);
+#pragma unroll
+  for (int c1 = 0; c1 < 4; ++c1) {
+    const T row = G[4 * c1 + 0] * nbval(X, kVS.v[t][a][0]) + G[4 * c1 + 1] * nbval(X, kVS.v[t][a][1]) +
+                  G[4 * c1 + 2] * nbval(X, kVS.v[t][a][2]) + G[4 * c1 + 3] * nbval(X, kVS.v[t][a][3]);
+    bil += nbval(R, kVS.v[t][a][c1]) * row;
+  }
+  acc += tet_exists<t, a>(z) ? bil : T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ T kgrad_row(const TypeGeo<T> *g, const T R[3][7], const T X[3][7], int z) {
+  T acc = T(0);
+  kgrad_tet<T, 0, 0>(g, R, X, z, acc); kgrad_tet<T, 0, 1>(g, R, X, z, acc);
+  kgrad_tet<T, 0, 2>(g, R, X, z, acc); kgrad_tet<T, 0, 3>(g, R, X, z, acc);
+  kgrad_tet<T, 1, 0>(g, R, X, z, acc); kgrad_tet<T, 1, 1>(g, R, X, z, acc);
+  kgrad_tet<T, 1, 2>(g, R, X, z, acc); kgrad_tet<T, 1, 3>(g, R, X, z, acc);
+  kgrad_tet<T, 2, 0>(g, R, X, z, acc); kgrad_tet<T, 2, 1>(g, R, X, z, acc);
+  kgrad_tet<T, 2, 2>(g, R, X, z, acc); kgrad_tet<T, 2, 3>(g, R, X, z, acc);
+  kgrad_tet<T, 3, 0>(g, R, X, z, acc); kgrad_tet<T, 3, 1>(g, R, X, z, acc);
+  kgrad_tet<T, 3, 2>(g, R, X, z, acc); kgrad_tet<T, 3, 3>(g, R, X, z, acc);
+  kgrad_tet<T, 4, 0>(g, R, X, z, acc); kgrad_tet<T, 4, 1>(g, R, X, z, acc);
+  kgrad_tet<T, 4, 2>(g, R, X, z, acc); kgrad_tet<T, 4, 3>(g, R, X, z, acc);
+  kgrad_tet<T, 5, 0>(g, R, X, z, acc); kgrad_tet<T, 5, 1>(g, R, X, z, acc);
+  kgrad_tet<T, 5, 2>(g, R, X, z, acc); kgrad_tet<T, 5, 3>(g, R, X, z, acc);
+  return acc * T(0.25);
+}
+
+// The 15-point neighbourhood of the points of one row chunk: row bases (in
+// the macro's block) of the 7 rows (j, k), (j+-1, k), (j, k+-1), (j+1, k-1),
+// (j-1, k+1); slot q of point (i, j, k) is at rb[row of q] + i + di(q).
+struct Rows {
+  int rb[3][3];  // [plane k-1, k, k+1][row j-1, j, j+1]
+};
+
+__device__ __forceinline__ Rows chunk_rows(int j, int k, int N) {
+  Rows R;
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int kk = k + p - 1, jj = j + r - 1;
+      const int M = N - kk;
+      R.rb[p][r] = c3(N) - c3(M) + (jj * (2 * M + 3 - jj)) / 2;
+    }
+  return R;
+}
+
+// values of v at the neighbourhood of (i, j, k).  CHECK: points outside the
+// lattice read 0, and with MASK Dirichlet DoFs read 0 too.
+template <typename T, bool CHECK, bool MASK>
+__device__ __forceinline__ void gather15(const T *__restrict__ v, const Rows &R, int i, int j, int k, int N,
+                                         uint32_t bnd, T P[3][7]) {
+#pragma unroll
+  for (int q = 0; q < 15; ++q) {
+    const int di = kNb[q][0], dj = kNb[q][1], dk = kNb[q][2];
+    const int ii = i + di, jj = j + dj, kk = k + dk;
+    bool ok = true;
+    if (CHECK) {
+      ok = ii >= 0 && jj >= 0 && kk >= 0 && ii + jj + kk <= N;
+      if (MASK) ok = ok && !((bnd >> zero_pattern(ii, jj, kk, N)) & 1u);
+    }
+    T val = T(0);
+    if (ok) val = v[R.rb[dk + 1][dj + 1] + ii];
+    P[kNbPlane[q]][kNbSlot[q]] = val;
+  }
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
+// Renumber them so that XCD x runs one contiguous run of the (macro, chunk
+// block) sequence, in order: neighbouring rows and planes -- the 15-point
+// neighbourhoods -- are then read through the same L2.
+__device__ __forceinline__ void xcd_block(int nchunks, int *m, int *cb) {
+  const int per_macro = (nchunks + 3) / 4;
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int x8 = b & 7, q = nb >> 3, rem = nb & 7;
+  const int t = x8 * q + min(x8, rem) + (b >> 3);
+  *m = t / per_macro;
+  *cb = t - *m * per_macro;
+}
+
+// One wavefront per row chunk (up to 64 consecutive points of one lattice
+// row); a 1-D grid of ceil(chunks / 4) * macros workgroups of 4 wavefronts.
 template <typename T, int KIND>
-__global__ __launch_bounds__(256) void k_p1_apply(P1Args<T> a) {
+__global__ __launch_bounds__(256) void k_p1_apply(P1Args<T> a, const int4 *__restrict__ chunks, int nchunks) {
   constexpr bool VARK = KIND == P1_DIVKGRAD;
   const LatticeArgs<T> &L = a.lat;
-  const int m = blockIdx.y;
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= L.L) return;
   const int N = L.N;
-  int i, j, k;
-  decode(r, N, i, j, k);
+  int m, cb;
+  xcd_block(nchunks, &m, &cb);
+  const int ch = cb * 4 + (threadIdx.x >> 6);
+  if (ch >= nchunks) return;
+  const int4 c = chunks[ch];  // j, k, i0, length
+  const int j = c.x, k = c.y, i = c.z + (threadIdx.x & 63);
+  if (i >= c.z + c.w) return;
   const int64_t base = static_cast<int64_t>(m) * L.L;
   const uint32_t bnd = L.bnd[m];
-  if (L.dirichlet && is_bnd(bnd, i, j, k, N)) {
-    a.y[base + r] = T(0);
-    return;
-  }
+  const Rows R = chunk_rows(j, k, N);
   const T *x = a.x + base;
   const T *kc = VARK ? a.k + base : nullptr;
   const TypeGeo<T> *g = L.geo + 6 * m;
   const int d = L.dirichlet ? 2 : 1;
-  const int s = i + j + k;
-  T xs[15], ks[15];
-  T acc;
-  if (i >= d && j >= d && k >= d && s <= N - d) {
-    load15<T, false>(x, i, j, k, N, false, bnd, xs);
+  // every point of the chunk at distance >= d from each macro face: all 24
+  // micro-tets exist and no neighbour is a Dirichlet DoF
+  const bool inner = j >= d && k >= d && c.z >= d && c.z + c.w - 1 + j + k <= N - d;
+  T X[3][7], K[3][7];
+  T acc = T(0);
+  if (inner) {
+    gather15<T, false, false>(x, R, i, j, k, N, bnd, X);
     if (VARK) {
-      load15<T, false>(kc, i, j, k, N, false, bnd, ks);
-      acc = p1_row<T, true, false>(g, xs, ks, i, j, k, N);
+      gather15<T, false, false>(kc, R, i, j, k, N, bnd, K);
+      acc = p1k_row(g, X, K, 0);
     } else {
-      const T *w = a.w15 + 15 * m;
-      acc = T(0);
+      const T *w = a.w15 + 16 * 15 * m;  // class 0: the interior stencil
 #pragma unroll
-      for (int q = 0; q < 15; ++q) acc += w[q] * xs[q];
+      for (int q = 0; q < 15; ++q) acc += w[q] * nbval(X, q);
     }
   } else {
-    load15<T, true>(x, i, j, k, N, L.dirichlet != 0, bnd, xs);
-    if (VARK) load15<T, true>(kc, i, j, k, N, false, bnd, ks);
-    acc = p1_row<T, VARK, true>(g, xs, ks, i, j, k, N);
-  }
-  a.y[base + r] = acc;
-}
-
-// Fused reverse mode of y = A(k) x for the P1 div(k grad) operator:
-//   gx_p = (A(k) gy)_p
-//   gk_p = sum_{T containing p} 1/4 (D gy)_T . Gp_T (D x)_T
-// (A_T = kbar_T Gp_T with kbar_T the mean of the four nodal k of T).
-template <typename T, bool CHECK>
-__device__ inline T p1_kgrad(const TypeGeo<T> *__restrict__ g, const T rs[15], const T xs[15], int i,
-                             int j, int k, int N) {
-  T acc = T(0);
+    const int z = zero_pattern(i, j, k, N);
+    if (!(L.dirichlet && ((bnd >> z) & 1u))) {
+      if (L.dirichlet)
+        gather15<T, true, true>(x, R, i, j, k, N, bnd, X);
+      else
+        gather15<T, true, false>(x, R, i, j, k, N, bnd, X);
+      if (VARK) {
+        gather15<T, true, false>(kc, R, i, j, k, N, bnd, K);
+        acc = p1k_row(g, X, K, z);
+      } else {
+        const T *w = a.w15 + (16 * m + z) * 15;
 #pragma unroll
-  for (int t = 0; t < 6; ++t) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      if (tet_exists<CHECK>(t, a, i, j, k, N)) {
-        const T *G = g[t].Gp;
-        T bil = T(0);
-#pragma unroll
-        for (int c1 = 0; c1 < 4; ++c1) {
-          T row = G[4 * c1 + 0] * xs[kVS.v[t][a][0]];
-          row += G[4 * c1 + 1] * xs[kVS.v[t][a][1]];
-          row += G[4 * c1 + 2] * xs[kVS.v[t][a][2]];
-          row += G[4 * c1 + 3] * xs[kVS.v[t][a][3]];
-          bil += rs[kVS.v[t][a][c1]] * row;
-        }
-        acc += bil;
+        for (int q = 0; q < 15; ++q) acc += w[q] * nbval(X, q);
       }
     }
   }
-  return acc * T(0.25);
+  a.y[base + R.rb[1][1] + i] = acc;
 }
 
+// Fused reverse mode of the macro-local P1 div(k grad) apply:
+//   gx_p = (L(k) gy)_p,  gk_p = sum_{T containing p} 1/4 (D gy)_T . Gp_T (D x)_T
 template <typename T>
-__global__ __launch_bounds__(256) void k_p1_adjoint(P1AdjArgs<T> a) {
+__global__ __launch_bounds__(256) void k_p1_adjoint(P1AdjArgs<T> a, const int4 *__restrict__ chunks, int nchunks) {
   const LatticeArgs<T> &L = a.lat;
-  const int m = blockIdx.y;
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= L.L) return;
   const int N = L.N;
-  int i, j, k;
-  decode(r, N, i, j, k);
+  int m, cb;
+  xcd_block(nchunks, &m, &cb);
+  const int ch = cb * 4 + (threadIdx.x >> 6);
+  if (ch >= nchunks) return;
+  const int4 c = chunks[ch];
+  const int j = c.x, k = c.y, i = c.z + (threadIdx.x & 63);
+  if (i >= c.z + c.w) return;
   const int64_t base = static_cast<int64_t>(m) * L.L;
   const uint32_t bnd = L.bnd[m];
+  const Rows R = chunk_rows(j, k, N);
   const TypeGeo<T> *g = L.geo + 6 * m;
-  const bool self_bnd = L.dirichlet && is_bnd(bnd, i, j, k, N);
   const int d = L.dirichlet ? 2 : 1;
-  const int s = i + j + k;
-  T rs[15], xs[15], ks[15];
-  T gx, gk;
-  if (i >= d && j >= d && k >= d && s <= N - d) {
-    load15<T, false>(a.gy + base, i, j, k, N, false, bnd, rs);
-    load15<T, false>(a.x + base, i, j, k, N, false, bnd, xs);
-    load15<T, false>(a.k + base, i, j, k, N, false, bnd, ks);
-    gx = p1_row<T, true, false>(g, rs, ks, i, j, k, N);
-    gk = p1_kgrad<T, false>(g, rs, xs, i, j, k, N);
+  const bool inner = j >= d && k >= d && c.z >= d && c.z + c.w - 1 + j + k <= N - d;
+  T G[3][7], X[3][7], K[3][7];
+  int z = 0;
+  if (inner) {
+    gather15<T, false, false>(a.gy + base, R, i, j, k, N, bnd, G);
+    gather15<T, false, false>(a.x + base, R, i, j, k, N, bnd, X);
+    gather15<T, false, false>(a.k + base, R, i, j, k, N, bnd, K);
   } else {
-    const bool mask = L.dirichlet != 0;
-    load15<T, true>(a.gy + base, i, j, k, N, mask, bnd, rs);
-    load15<T, true>(a.x + base, i, j, k, N, mask, bnd, xs);
-    load15<T, true>(a.k + base, i, j, k, N, false, bnd, ks);
-    gx = self_bnd ? T(0) : p1_row<T, true, true>(g, rs, ks, i, j, k, N);
-    gk = p1_kgrad<T, true>(g, rs, xs, i, j, k, N);
+    z = zero_pattern(i, j, k, N);
+    if (L.dirichlet) {
+      gather15<T, true, true>(a.gy + base, R, i, j, k, N, bnd, G);
+      gather15<T, true, true>(a.x + base, R, i, j, k, N, bnd, X);
+    } else {
+      gather15<T, true, false>(a.gy + base, R, i, j, k, N, bnd, G);
+      gather15<T, true, false>(a.x + base, R, i, j, k, N, bnd, X);
+    }
+    gather15<T, true, false>(a.k + base, R, i, j, k, N, bnd, K);
   }
-  a.gx[base + r] = gx;
-  if (a.gk) a.gk[base + r] = gk;
+  const bool self_bnd = L.dirichlet && ((bnd >> z) & 1u);
+  const int64_t slot = base + R.rb[1][1] + i;
+  a.gx[slot] = self_bnd ? T(0) : p1k_row(g, G, K, z);
+  if (a.gk) a.gk[slot] = kgrad_row(g, G, X, z);
 }
 
 }  // namespace
 
 template <typename T>
-hipError_t launch_p1_apply(const P1Args<T> &a, int kind, hipStream_t s) {
-  dim3 grid((a.lat.L + 255) / 256, a.lat.nt);
+hipError_t launch_p1_apply(const P1Args<T> &a, int kind, const int4 *chunks, int nchunks, hipStream_t s) {
+  const dim3 grid(((nchunks + 3) / 4) * a.lat.nt);
   if (kind == P1_LAPLACE)
-    hipLaunchKernelGGL((k_p1_apply<T, P1_LAPLACE>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_p1_apply<T, P1_LAPLACE>), grid, dim3(256), 0, s, a, chunks, nchunks);
   else
-    hipLaunchKernelGGL((k_p1_apply<T, P1_DIVKGRAD>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_p1_apply<T, P1_DIVKGRAD>), grid, dim3(256), 0, s, a, chunks, nchunks);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_p1_adjoint(const P1AdjArgs<T> &a, hipStream_t s) {
-  dim3 grid((a.lat.L + 255) / 256, a.lat.nt);
-  hipLaunchKernelGGL((k_p1_adjoint<T>), grid, dim3(256), 0, s, a);
+hipError_t launch_p1_adjoint(const P1AdjArgs<T> &a, const int4 *chunks, int nchunks, hipStream_t s) {
+  const dim3 grid(((nchunks + 3) / 4) * a.lat.nt);
+  hipLaunchKernelGGL((k_p1_adjoint<T>), grid, dim3(256), 0, s, a, chunks, nchunks);
   return hipGetLastError();
 }
 
-template hipError_t launch_p1_apply<double>(const P1Args<double> &, int, hipStream_t);
-template hipError_t launch_p1_apply<float>(const P1Args<float> &, int, hipStream_t);
-template hipError_t launch_p1_adjoint<double>(const P1AdjArgs<double> &, hipStream_t);
-template hipError_t launch_p1_adjoint<float>(const P1AdjArgs<float> &, hipStream_t);
+template hipError_t launch_p1_apply<double>(const P1Args<double> &, int, const int4 *, int, hipStream_t);
+template hipError_t launch_p1_apply<float>(const P1Args<float> &, int, const int4 *, int, hipStream_t);
+template hipError_t launch_p1_adjoint<double>(const P1AdjArgs<double> &, const int4 *, int, hipStream_t);
+template hipError_t launch_p1_adjoint<float>(const P1AdjArgs<float> &, const int4 *, int, hipStream_t);
 
 }  // namespace tmf

@@ -97,7 +97,7 @@ struct LatticeArgs {
 template <typename T>
 struct P1Args {
   LatticeArgs<T> lat;
-  const T *w15;  // per macro: 15-point stencil of the constant-coefficient operator
+  const T *w15;  // per macro, per boundary class (16): 15-point stencil of the constant-coefficient operator
   const T *k;
   const T *x;
   T *y;
@@ -152,9 +152,9 @@ constexpr int kQStride = 45;  // floats per quadrature point in qtab
 
 // launchers (kernels.hip); return the HIP error of the launch
 template <typename T>
-hipError_t launch_p1_apply(const P1Args<T> &a, int kind, hipStream_t s);
+hipError_t launch_p1_apply(const P1Args<T> &a, int kind, const int4 *chunks, int nchunks, hipStream_t s);
 template <typename T>
-hipError_t launch_p1_adjoint(const P1AdjArgs<T> &a, hipStream_t s);
+hipError_t launch_p1_adjoint(const P1AdjArgs<T> &a, const int4 *chunks, int nchunks, hipStream_t s);
 template <typename T>
 hipError_t launch_tile_apply(const TileArgs<T> &a, int kind, int map, int tile_cfg, hipStream_t s);
 template <typename T>
