@@ -40,10 +40,16 @@ __global__ __launch_bounds__(kBlasThreads) void k_dot_partial(const TA *a, const
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// out[i] = sum of the partials of instance i, in chunk order
+// Sum of the partials of instance i, by one wavefront: lane l adds partials
+// first[i] + l, + 64, ... in order, then a fixed xor butterfly.  Every lane
+// ends with the same bits (a + b == b + a exactly), and the order depends only
+// on the chunk list, so the result is reproducible run to run.
 __device__ inline double inst_sum(const double *partial, const int *first, int i) {
+  const int lane = threadIdx.x & 63;
   double s = 0;
-  for (int q = first[i]; q < first[i + 1]; ++q) s += partial[q];
+  for (int q = first[i] + lane; q < first[i + 1]; q += 64) s += partial[q];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   return s;
 }
 
@@ -73,9 +79,10 @@ __global__ __launch_bounds__(kBlasThreads) void k_residual(const double *b, cons
 // per instance: |r|, |b|, outer activity (|r| > tol |b|)
 __global__ void k_outer_norms(const double *prr, const double *pbb, const int *first, int count, double tol,
                               CgScalars s) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x;
   if (i >= count) return;
   const double rn = sqrt(inst_sum(prr, first, i)), bn = sqrt(inst_sum(pbb, first, i));
+  if (threadIdx.x != 0) return;
   s.rnorm[i] = rn;
   s.bnorm[i] = bn;
   s.oact[i] = (rn > tol * bn) ? 1 : 0;
@@ -103,9 +110,10 @@ __global__ __launch_bounds__(kBlasThreads) void k_scale_cast(const double *r64, 
 }
 
 __global__ void k_cg_init(const double *partial, const int *first, int count, CgScalars s) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x;
   if (i >= count) return;
   const double rr = inst_sum(partial, first, i);
+  if (threadIdx.x != 0) return;
   s.rr[i] = rr;
   s.rr0[i] = rr;
   s.iact[i] = (s.oact[i] && rr > 0) ? 1 : 0;
@@ -114,9 +122,10 @@ __global__ void k_cg_init(const double *partial, const int *first, int count, Cg
 
 // alpha = rr / (p.q) for inner-active instances, else 0
 __global__ void k_cg_alpha(const double *partial, const int *first, int count, CgScalars s) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x;
   if (i >= count) return;
   const double pq = inst_sum(partial, first, i);
+  if (threadIdx.x != 0) return;
   s.alpha[i] = (s.iact[i] && pq > 0) ? s.rr[i] / pq : 0.0;
 }
 
@@ -142,13 +151,14 @@ __global__ __launch_bounds__(kBlasThreads) void k_cg_update(float *d, float *r, 
 // beta = rr_new / rr; convergence test of the inner iteration
 __global__ void k_cg_beta(const double *partial, const int *first, int count, double rtol2, int maxit,
                           CgScalars s) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x;
   if (i >= count) return;
   if (!s.iact[i]) {
-    s.beta[i] = 0.0;
+    if (threadIdx.x == 0) s.beta[i] = 0.0;
     return;
   }
   const double rrn = inst_sum(partial, first, i);
+  if (threadIdx.x != 0) return;
   s.beta[i] = rrn / s.rr[i];
   s.rr[i] = rrn;
   const int it = s.it[i] + 1;
@@ -192,23 +202,23 @@ __global__ __launch_bounds__(kBlasThreads) void k_update_x(double *x, const floa
 hipError_t blas_residual(const BlasCtx &c, const double *b, const double *Ax, double *r, double *prr, double *pbb,
                          double tol, hipStream_t s) {
   TMF_LAUNCH(k_residual, c.nchunks, kBlasThreads, s, b, Ax, r, c.owner, c.chunks, prr, pbb);
-  TMF_LAUNCH(k_outer_norms, (c.count + 63) / 64, 64, s, prr, pbb, c.first, c.count, tol, c.sc);
+  TMF_LAUNCH(k_outer_norms, c.count, 64, s, prr, pbb, c.first, c.count, tol, c.sc);
   return hipSuccess;
 }
 
 hipError_t blas_start_inner(const BlasCtx &c, const double *r64, float *r32, float *p, float *d, double *part,
                             hipStream_t s) {
   TMF_LAUNCH(k_scale_cast, c.nchunks, kBlasThreads, s, r64, r32, p, d, c.owner, c.chunks, c.sc, part);
-  TMF_LAUNCH(k_cg_init, (c.count + 63) / 64, 64, s, part, c.first, c.count, c.sc);
+  TMF_LAUNCH(k_cg_init, c.count, 64, s, part, c.first, c.count, c.sc);
   return hipSuccess;
 }
 
 hipError_t blas_cg_step_after_apply(const BlasCtx &c, float *d, float *r, float *p, const float *q, double *part,
                                     double rtol2, int maxit, hipStream_t s) {
   TMF_LAUNCH((k_dot_partial<float, float>), c.nchunks, kBlasThreads, s, p, q, c.owner, c.chunks, part);
-  TMF_LAUNCH(k_cg_alpha, (c.count + 63) / 64, 64, s, part, c.first, c.count, c.sc);
+  TMF_LAUNCH(k_cg_alpha, c.count, 64, s, part, c.first, c.count, c.sc);
   TMF_LAUNCH(k_cg_update, c.nchunks, kBlasThreads, s, d, r, p, q, c.owner, c.chunks, c.sc, part);
-  TMF_LAUNCH(k_cg_beta, (c.count + 63) / 64, 64, s, part, c.first, c.count, rtol2, maxit, c.sc);
+  TMF_LAUNCH(k_cg_beta, c.count, 64, s, part, c.first, c.count, rtol2, maxit, c.sc);
   TMF_LAUNCH(k_cg_p, c.nchunks, kBlasThreads, s, p, r, c.chunks, c.sc);
   return hipSuccess;
 }
