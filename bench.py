@@ -140,8 +140,10 @@ def n_elements(mesh_nt, level):
     return mesh_nt * n ** 3
 
 
-def traffic_for(kernel_key):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they match the current source."""
+def traffic_for(kernel_key, tile):
+    """HBM bytes per launch of one element-kernel tile shape, from the committed rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a 1 GiB copy); None when the kernel
+    source has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -154,7 +156,7 @@ def traffic_for(kernel_key):
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     if h != ent.get("source_sha256_16"):
         return None
-    return ent["bytes_per_launch"]
+    return ent["bytes_per_launch_by_tile"].get("x".join(str(v) for v in tile))
 
 
 def batched_solve(torch, T, W, hip, steps):
@@ -275,7 +277,7 @@ def main():
         achieved, peak, unit = flops / (kern * 1e-3) / 1e12, PEAK_FP64 / 1e12, "TFLOP/s"
     else:
         achieved, peak, unit = bytes_alg / (kern * 1e-3) / 1e9, PEAK_HBM / 1e9, "GB/s"
-    traffic = traffic_for("p2_divkgrad_fp64_cube6")
+    traffic = traffic_for("p2_divkgrad_fp64_cube6", (tx.value, ty.value, tz.value))
     value = op.n_unique / (wall * 1e-3) / 1e6
     out = {
         "metric": "operator-apply MDoF/s (FP64 vs FP32-refined, fwd+adjoint) and % HBM roofline",
