@@ -25,6 +25,18 @@ __device__ inline bool is_bnd(uint32_t bnd, int i, int j, int k, int N) {
   return (bnd >> zero_pattern(i, j, k, N)) & 1u;
 }
 
+// Per-type geometry and quadrature tables are read-only for the whole launch
+// and indexed by wave-uniform values (type, quadrature point).  Reading them
+// through the constant address space turns the reads into scalar loads kept
+// in SGPRs; through a generic pointer they would be per-lane flat loads whose
+// completion every later LDS wait also has to cover.
+template <typename T>
+using CPtr = const __attribute__((address_space(4))) T *;
+template <typename T>
+__device__ __forceinline__ CPtr<T> cptr(const T *p) {
+  return (CPtr<T>)p;
+}
+
 // Exact weights W_ce = (1/|T|) int_T k lambda_c lambda_e for k nodal P2.
 // k in Bernstein form: k = sum_b kappa_b B_b, B_aa = lambda_a^2,
 // B_ab = 2 lambda_a lambda_b, kappa_aa = k_a, kappa_ab = 2 k_ab - (k_a + k_b)/2.
@@ -97,7 +109,7 @@ __device__ inline void grad_coeffs(const T u[10], T sp[4][3]) {
 // (from grad phi_b = (4 lambda_b - 1) grad lambda_b and
 //  grad phi_bc = 4 (lambda_c grad lambda_b + lambda_b grad lambda_c)).
 template <typename T, bool HASK>
-__device__ inline void p2_elem(const T u[10], const T kv[10], const T *__restrict__ Gp, T y[10]) {
+__device__ inline void p2_elem(const T u[10], const T kv[10], CPtr<T> Gp, T y[10]) {
   T sp[4][3];
   grad_coeffs(u, sp);
   T h[4][4];
@@ -143,8 +155,7 @@ __device__ inline void p2_elem(const T u[10], const T kv[10], const T *__restric
 //   y_vertex b = 2|T| (4 sigma_b - sum_e sigma_e) grad lambda_b
 //   y_edge bc  = 8|T| (sigma_c grad lambda_b + sigma_b grad lambda_c)
 template <typename T>
-__device__ inline void eps_elem(const T u[3][10], const T mu[10], const T *__restrict__ grad, T vol,
-                                T y[3][10]) {
+__device__ inline void eps_elem(const T u[3][10], const T mu[10], CPtr<T> grad, T vol, T y[3][10]) {
   // g[c][a][r]
   T E[4][6];  // symmetric strain per vertex: xx, yy, zz, xy, xz, yz
   {
@@ -181,7 +192,7 @@ __device__ inline void eps_elem(const T u[3][10], const T mu[10], const T *__res
       sig[e][q] = W[0][e] * E[0][q] + W[1][e] * E[1][q] + W[2][e] * E[2][q] + W[3][e] * E[3][q];
       tot[q] += sig[e][q];
     }
-  auto matvec = [](const T S[6], const T *v, T out[3]) {
+  auto matvec = [](const T S[6], CPtr<T> v, T out[3]) {
     out[0] = S[0] * v[0] + S[3] * v[1] + S[4] * v[2];
     out[1] = S[3] * v[0] + S[1] * v[1] + S[5] * v[2];
     out[2] = S[4] * v[0] + S[5] * v[1] + S[2] * v[2];
@@ -213,15 +224,14 @@ __device__ inline void eps_elem(const T u[3][10], const T mu[10], const T *__res
 //   grad u_c = (ref-grad u_c) J^-1,  sigma = 2 mu_q w_q |det J| sym(grad u),
 //   y_(i,d) += sum_r (sigma J^-T)_(d r) ref-grad_r phi_i(xhat_q).
 template <typename T>
-__device__ inline void eps_blended_elem(const T u[3][10], const T mu[10], const T P0[3],
-                                        const T *__restrict__ JT, const T s[3],
-                                        const T *__restrict__ qtab, int nq, T y[3][10]) {
+__device__ inline void eps_blended_elem(const T u[3][10], const T mu[10], const T P0[3], CPtr<T> JT,
+                                        const T s[3], CPtr<T> qtab, int nq, T y[3][10]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int i = 0; i < 10; ++i) y[c][i] = T(0);
   for (int q = 0; q < nq; ++q) {
-    const T *Q = qtab + q * kQStride;  // w, bary[4], phi[10], refgrad[10][3]
+    CPtr<T> Q = qtab + q * kQStride;  // w, bary[4], phi[10], refgrad[10][3]
     const T xh[3] = {Q[2], Q[3], Q[4]};
     T xi[3];
 #pragma unroll
@@ -257,7 +267,7 @@ __device__ inline void eps_blended_elem(const T u[3][10], const T mu[10], const 
     for (int r = 0; r < 3; ++r)
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) Ji[r][cc] *= idet;
-    const T *RG = Q + 15;
+    CPtr<T> RG = Q + 15;
     T gr[3][3];  // reference gradient of each component
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -323,16 +333,18 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
       mu[v] = sk[li[v]];
     }
     if constexpr (MAP == 0) {
-      eps_elem(u, mu, g->grad, g->vol, y);
+      eps_elem(u, mu, cptr(g->grad), *cptr(&g->vol), y);
     } else {
-      const MacroGeo<T> &mg = D->mgeo[m];
+      const __attribute__((address_space(4))) MacroGeo<T> &mg =
+          *(const __attribute__((address_space(4))) MacroGeo<T> *)(D->mgeo + m);
       const T bc[3] = {T(bxc + kOff[t][0][0]), T(byc + kOff[t][0][1]), T(bzc + kOff[t][0][2])};
       const T inv_n = T(1) / T(D->n);
       T P0[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d)
         P0[d] = mg.v0[d] + (mg.JM[3 * d + 0] * bc[0] + mg.JM[3 * d + 1] * bc[1] + mg.JM[3 * d + 2] * bc[2]) * inv_n;
-      eps_blended_elem(u, mu, P0, g->JT, mg.s, a.qtab, a.nq, y);
+      const T sv[3] = {mg.s[0], mg.s[1], mg.s[2]};
+      eps_blended_elem(u, mu, P0, cptr(g->JT), sv, cptr(a.qtab), a.nq, y);
     }
 #pragma unroll
     for (int v = 0; v < 10; ++v)
@@ -346,7 +358,7 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
       u[v] = sx[0][li[v]];
       kv[v] = HASK ? sk[li[v]] : T(1);
     }
-    p2_elem<T, HASK>(u, kv, g->Gp, y);
+    p2_elem<T, HASK>(u, kv, cptr(g->Gp), y);
 #pragma unroll
     for (int v = 0; v < 10; ++v) atomicAdd(&sy[0][li[v]], double(y[v]));
   }
@@ -424,7 +436,8 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
     const int t = __builtin_amdgcn_readfirstlane(e / C);
     const int c = e - t * C;
     const int cx = c % TX, cy = (c / TX) % TY, cz = c / (TX * TY);
-    if (s0 + cx + cy + cz > n - kLim[t]) continue;
+    const int lim = 1 + (t > 0) + (t == 5);  // kLim[t] without a table load
+    if (s0 + cx + cy + cz > n - lim) continue;
     const int cb = 2 * cx + RX * (2 * cy + RY * 2 * cz);
     int li[10];
 #pragma unroll
