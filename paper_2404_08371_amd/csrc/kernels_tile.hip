@@ -311,17 +311,21 @@ struct TileCfg {
   static constexpr int C = TX * TY * TZ;
   static constexpr int NC = KIND == P2V_EPSILON ? 3 : 1;
   static constexpr bool HASK = KIND != P2_LAPLACE;
-  // 4 waves per workgroup: with the FP64 element code (~96 VGPRs) this keeps
-  // four workgroups resident per CU, where 12-wave groups fit only one
-  static constexpr int NTH = 256;
-  static_assert(C % 64 == 0, "one micro-tet type per wavefront needs 64 | cubes per tile");
+  // 6 wavefronts per workgroup, wavefront w applying micro-tet type w to every
+  // cube of the box: the type is a compile-time constant inside each
+  // wavefront's loop (LDS node offsets become instruction immediates, the
+  // type's geometry is loaded once into scalar registers)
+  // (the epsilon element needs 124-235 VGPRs: there 4-wavefront groups, two
+  // per CU, beat one 6-wavefront group; wavefronts then take (type, cube)
+  // slots with a wave-uniform type)
+  static constexpr int NTH = KIND == P2V_EPSILON ? 256 : 384;
+  static_assert(C % 64 == 0, "every lane of a wavefront needs a cube: 64 | cubes per tile");
 };
 
 // one micro-tet whose 10 local nodes sit at LDS points li[]
-template <typename T, int KIND, int MAP, int R>
+template <typename T, int KIND, int MAP, int R, int t>
 __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T> *D, T (*sx)[R], const T *sk,
-                                          double (*sy)[R], const int li[10], int t, int m, int bxc, int byc,
-                                          int bzc) {
+                                          double (*sy)[R], const int li[10], int m, int bxc, int byc, int bzc) {
   const TypeGeo<T> *g = D->geo + 6 * m + t;
   if constexpr (KIND == P2V_EPSILON) {
     T u[3][10], mu[10], y[3][10];
@@ -364,6 +368,38 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
   }
 }
 
+// LDS offset of local node v of a type-t micro-tet from its cube's base
+// point, in a box row-major with row lengths RX, RY (P2 lattice: vertex p ->
+// 2p, edge (p, q) -> p + q)
+constexpr int node_off(int t, int v, int RX, int RY) {
+  int o[3] = {0, 0, 0};
+  for (int d = 0; d < 3; ++d)
+    o[d] = v < 4 ? 2 * kOff[t][v][d] : kOff[t][kEdge[v - 4][0]][d] + kOff[t][kEdge[v - 4][1]][d];
+  return o[0] + RX * (o[1] + RY * o[2]);
+}
+
+// micro-tet of type t in cube c of the box (x fastest), if it exists
+template <typename T, int KIND, int MAP, int TX, int TY, int TZ, int t, int R>
+__device__ __forceinline__ void cube_elem(const TileArgs<T> &a, const InstDesc<T> *D, T (*sx)[R], const T *sk,
+                                          double (*sy)[R], int m, int bx0, int by0, int bz0, int c) {
+  constexpr int RX = 2 * TX + 1, RY = 2 * TY + 1;
+  const int cx = c % TX, cy = (c / TX) % TY, cz = c / (TX * TY);
+  if (bx0 + by0 + bz0 + cx + cy + cz > D->n - kLim[t]) return;
+  const int cb = 2 * cx + RX * (2 * cy + RY * 2 * cz);
+  int li[10];
+#pragma unroll
+  for (int v = 0; v < 10; ++v) li[v] = cb + node_off(t, v, RX, RY);
+  tile_elem<T, KIND, MAP, R, t>(a, D, sx, sk, sy, li, m, bx0 + cx, by0 + cy, bz0 + cz);
+}
+
+// every cube of the box, micro-tet type t; lane l takes cubes l, l + 64, ...
+template <typename T, int KIND, int MAP, int TX, int TY, int TZ, int t, int R>
+__device__ __forceinline__ void type_loop(const TileArgs<T> &a, const InstDesc<T> *D, T (*sx)[R], const T *sk,
+                                          double (*sy)[R], int m, int bx0, int by0, int bz0, int lane) {
+  constexpr int C = TX * TY * TZ;
+  for (int c = lane; c < C; c += 64) cube_elem<T, KIND, MAP, TX, TY, TZ, t, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, c);
+}
+
 // One workgroup per tile.  Workgroup ids are dispatched round-robin over the
 // 8 XCDs; the id -> tile map below is a bijection that gives every XCD a
 // contiguous run of the (spatially ordered) tile list, so neighbouring boxes
@@ -379,7 +415,6 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
   // pipeline, and the partial sums of a point keep 53-bit mantissas
   __shared__ double sy[NC][R];
   __shared__ T sk[HASK ? R : 1];
-  __shared__ int snoff[6][10];
 
   const int tid = threadIdx.x;
   const int nxcd = 8;
@@ -391,77 +426,118 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
   if (a.active != nullptr && a.active[tl.x] == 0) return;
   const int m = tl.y;
   const int bx0 = tl.z & 1023, by0 = (tl.z >> 10) & 1023, bz0 = (tl.z >> 20) & 1023;
-  const int N = D->N, n = D->n;
+  const int N = D->N;
   const int64_t nl = D->n_local;
   const uint32_t bnd = D->dirichlet ? D->bnd[m] : 0u;
   const int64_t base = D->off + static_cast<int64_t>(m) * D->L;
 
-  if (tid < 60) {
-    const int t = tid / 10, v = tid % 10;
-    int o[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-      o[d] = v < 4 ? 2 * kOff[t][v][d] : kOff[t][kEdge[v - 4][0]][d] + kOff[t][kEdge[v - 4][1]][d];
-    snoff[t][v] = o[0] + RX * (o[1] + RY * o[2]);
+  // 0. the box's lattice rows (qj, qk): start offset in the macro block, and
+  // packed facts shared by the row's points -- (N - qj - qk) << 8, bit 2/3
+  // qj/qk = 0, bit 4 the row is owned by this box in y and z (write-back)
+  __shared__ int srb[RY * Cfg::RZ];
+  __shared__ int sri[RY * Cfg::RZ];
+  for (int row = tid; row < RY * Cfg::RZ; row += NTH) {
+    const int ry = row % RY, rz = row / RY;
+    const int qj = 2 * by0 + ry, qk = 2 * bz0 + rz;
+    const int lim = N - qj - qk;
+    srb[row] = lim >= 0 ? row_base(qj, qk, N) : 0;
+    const bool ey = (ry & 1) || ((ry > 0 || by0 == 0) && ry < 2 * TY);
+    const bool ez = (rz & 1) || ((rz > 0 || bz0 == 0) && rz < 2 * TZ);
+    sri[row] = (lim << 8) | ((qj == 0) << 2) | ((qk == 0) << 3) | ((ey && ez) << 4);
   }
-  // 1. stage the box: x with Dirichlet DoFs zeroed, and the coefficient
-  for (int r = tid; r < R; r += NTH) {
-    const int rx = r % RX, ry = (r / RX) % RY, rz = r / (RX * RY);
-    const int qi = 2 * bx0 + rx, qj = 2 * by0 + ry, qk = 2 * bz0 + rz;
-    T xv[NC], kv = T(0);
+  __syncthreads();
+  const T *xb[NC];
+  T *yb[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) xv[c] = T(0);
-    if (qi + qj + qk <= N) {
-      const int64_t gi = base + row_base(qj, qk, N) + qi;
-      if (!((bnd >> zero_pattern(qi, qj, qk, N)) & 1u)) {
+  for (int c = 0; c < NC; ++c) {
+    xb[c] = a.x + base + c * nl;
+    yb[c] = a.y + base + c * nl;
+  }
+  const T *kb = HASK ? a.k + base : nullptr;
+
+  // 1. stage the box: x with Dirichlet DoFs zeroed, and the coefficient.  The
+  // loop is unrolled over a thread's points so that all its loads are in
+  // flight together (one memory latency per tile instead of one per point).
+  constexpr int PF = (R + NTH - 1) / NTH;
+  T xv[PF][NC], kv[PF];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) xv[c] = a.x[gi + c * nl];
+  for (int p = 0; p < PF; ++p) {
+    const int r = tid + p * NTH;
+    kv[p] = T(0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) xv[p][c] = T(0);
+    if (r < R) {
+      const int row = r / RX, rx = r - row * RX;
+      const int info = sri[row], lim = info >> 8, qi = 2 * bx0 + rx;
+      if (qi <= lim) {
+        const int off = srb[row] + qi;
+        const int zp = (qi == lim) | ((qi == 0) << 1) | (info & 12);
+        if (!((bnd >> zp) & 1u)) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) xv[p][c] = xb[c][off];
+        }
+        if (HASK) kv[p] = kb[off];
       }
-      if (HASK) kv = a.k[gi];
     }
+  }
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      sx[c][r] = xv[c];
-      sy[c][r] = 0.0;
+  for (int p = 0; p < PF; ++p) {
+    const int r = tid + p * NTH;
+    if (r < R) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        sx[c][r] = xv[p][c];
+        sy[c][r] = 0.0;
+      }
+      if (HASK) sk[r] = kv[p];
     }
-    if (HASK) sk[r] = kv;
   }
   __syncthreads();
 
-  // 2. micro-tets: slot e -> (type e / C, cube e % C, x fastest); C is a
-  // multiple of 64, so the type is wave-uniform
-  constexpr int C = Cfg::C;
-  const int s0 = bx0 + by0 + bz0;
-  for (int e = tid; e < 6 * C; e += NTH) {
-    const int t = __builtin_amdgcn_readfirstlane(e / C);
-    const int c = e - t * C;
-    const int cx = c % TX, cy = (c / TX) % TY, cz = c / (TX * TY);
-    const int lim = 1 + (t > 0) + (t == 5);  // kLim[t] without a table load
-    if (s0 + cx + cy + cz > n - lim) continue;
-    const int cb = 2 * cx + RX * (2 * cy + RY * 2 * cz);
-    int li[10];
-#pragma unroll
-    for (int v = 0; v < 10; ++v) li[v] = cb + snoff[t][v];
-    tile_elem<T, KIND, MAP, R>(a, D, sx, sk, sy, li, t, m, bx0 + cx, by0 + cy, bz0 + cz);
+  // 2. micro-tets
+  if constexpr (NTH == 384) {
+    // wavefront w applies type w to every cube
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    switch (w) {
+      case 0: type_loop<T, KIND, MAP, TX, TY, TZ, 0, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
+      case 1: type_loop<T, KIND, MAP, TX, TY, TZ, 1, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
+      case 2: type_loop<T, KIND, MAP, TX, TY, TZ, 2, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
+      case 3: type_loop<T, KIND, MAP, TX, TY, TZ, 3, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
+      case 4: type_loop<T, KIND, MAP, TX, TY, TZ, 4, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
+      default: type_loop<T, KIND, MAP, TX, TY, TZ, 5, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
+    }
+  } else {
+    // slot e -> (type e / C, cube e % C); 64 | C makes the type wave-uniform
+    constexpr int C = Cfg::C;
+    for (int e = tid; e < 6 * C; e += NTH) {
+      const int t = __builtin_amdgcn_readfirstlane(e / C), c = e - t * C;
+      switch (t) {
+        case 0: cube_elem<T, KIND, MAP, TX, TY, TZ, 0, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
+        case 1: cube_elem<T, KIND, MAP, TX, TY, TZ, 1, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
+        case 2: cube_elem<T, KIND, MAP, TX, TY, TZ, 2, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
+        case 3: cube_elem<T, KIND, MAP, TX, TY, TZ, 3, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
+        case 4: cube_elem<T, KIND, MAP, TX, TY, TZ, 4, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
+        default: cube_elem<T, KIND, MAP, TX, TY, TZ, 5, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
+      }
+    }
   }
   __syncthreads();
 
   // 3. write back: points touched only by this box are stored, shared face points added
   for (int r = tid; r < R; r += NTH) {
-    const int rx = r % RX, ry = (r / RX) % RY, rz = r / (RX * RY);
-    const int qi = 2 * bx0 + rx, qj = 2 * by0 + ry, qk = 2 * bz0 + rz;
-    if (qi + qj + qk > N) continue;
-    if ((bnd >> zero_pattern(qi, qj, qk, N)) & 1u) continue;
-    const bool excl = ((rx & 1) || ((rx > 0 || bx0 == 0) && rx < 2 * TX)) &&
-                      ((ry & 1) || ((ry > 0 || by0 == 0) && ry < 2 * TY)) &&
-                      ((rz & 1) || ((rz > 0 || bz0 == 0) && rz < 2 * TZ));
-    const int64_t gi = base + row_base(qj, qk, N) + qi;
+    const int row = r / RX, rx = r - row * RX;
+    const int info = sri[row], lim = info >> 8, qi = 2 * bx0 + rx;
+    if (qi > lim) continue;
+    const int zp = (qi == lim) | ((qi == 0) << 1) | (info & 12);
+    if ((bnd >> zp) & 1u) continue;
+    const bool excl = ((info >> 4) & 1) && ((rx & 1) || ((rx > 0 || bx0 == 0) && rx < 2 * TX));
+    const int off = srb[row] + qi;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       if (excl)
-        a.y[gi + c * nl] = T(sy[c][r]);
+        yb[c][off] = T(sy[c][r]);
       else
-        atomicAdd(a.y + gi + c * nl, T(sy[c][r]));
+        atomicAdd(yb[c] + off, T(sy[c][r]));
     }
   }
 }
