@@ -307,7 +307,18 @@ __device__ inline void eps_blended_elem(const T u[3][10], const T mu[10], const 
 template <typename T, int KIND, int MAP, int TX, int TY, int TZ>
 struct TileCfg {
   static constexpr int RX = 2 * TX + 1, RY = 2 * TY + 1, RZ = 2 * TZ + 1;
-  static constexpr int R = RX * RY * RZ;
+  static constexpr int R = RX * RY * RZ;  // lattice points of the box
+  // LDS layout of a box row: the TX + 1 even-x points first, the TX odd-x
+  // points from slot OO, row pitch RXP.  Lane l of a wavefront works on cube
+  // x = l mod TX, so a given local node is read by consecutive lanes from
+  // consecutive 8-byte slots (the natural layout would stride by 2 and use
+  // half the banks), and the pitch puts the 16 / TX cube rows of a 16-lane
+  // group 8 TX bytes apart modulo 128: 2 RXP = TX (mod 16).
+  static constexpr int OO = TX + 1;
+  static constexpr int RXP = TX == 8 ? 20 : 10;
+  static constexpr int RP = RXP * RY * RZ;  // LDS slots per array
+  static_assert(TX == 4 || TX == 8, "row pitch chosen for TX = 4 or 8");
+  static_assert(RXP >= OO + TX && (2 * RXP - TX) % 16 == 0, "row pitch");
   static constexpr int C = TX * TY * TZ;
   static constexpr int NC = KIND == P2V_EPSILON ? 3 : 1;
   static constexpr bool HASK = KIND != P2_LAPLACE;
@@ -368,27 +379,32 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
   }
 }
 
-// LDS offset of local node v of a type-t micro-tet from its cube's base
-// point, in a box row-major with row lengths RX, RY (P2 lattice: vertex p ->
-// 2p, edge (p, q) -> p + q)
-constexpr int node_off(int t, int v, int RX, int RY) {
+// LDS slot of box point (rx, ry, rz) (x-parity split rows, pitch RXP)
+constexpr int lds_slot(int rx, int row, int OO, int RXP) { return ((rx & 1) ? OO + (rx >> 1) : (rx >> 1)) + RXP * row; }
+
+// LDS offset of local node v of a type-t micro-tet from its cube's slot
+// (P2 lattice: vertex p -> 2p, edge (p, q) -> p + q; the cube's base point
+// has even coordinates, so x offset 0 / 2 stays in the even half, 1 maps to
+// the odd half)
+constexpr int node_off(int t, int v, int RY, int OO, int RXP) {
   int o[3] = {0, 0, 0};
   for (int d = 0; d < 3; ++d)
     o[d] = v < 4 ? 2 * kOff[t][v][d] : kOff[t][kEdge[v - 4][0]][d] + kOff[t][kEdge[v - 4][1]][d];
-  return o[0] + RX * (o[1] + RY * o[2]);
+  return lds_slot(o[0], o[1] + RY * o[2], OO, RXP);
 }
 
 // micro-tet of type t in cube c of the box (x fastest), if it exists
 template <typename T, int KIND, int MAP, int TX, int TY, int TZ, int t, int R>
 __device__ __forceinline__ void cube_elem(const TileArgs<T> &a, const InstDesc<T> *D, T (*sx)[R], const T *sk,
                                           double (*sy)[R], int m, int bx0, int by0, int bz0, int c) {
-  constexpr int RX = 2 * TX + 1, RY = 2 * TY + 1;
+  using Cfg = TileCfg<T, KIND, MAP, TX, TY, TZ>;
+  constexpr int RY = Cfg::RY, OO = Cfg::OO, RXP = Cfg::RXP;
   const int cx = c % TX, cy = (c / TX) % TY, cz = c / (TX * TY);
   if (bx0 + by0 + bz0 + cx + cy + cz > D->n - kLim[t]) return;
-  const int cb = 2 * cx + RX * (2 * cy + RY * 2 * cz);
+  const int cb = cx + RXP * (2 * cy + RY * 2 * cz);
   int li[10];
 #pragma unroll
-  for (int v = 0; v < 10; ++v) li[v] = cb + node_off(t, v, RX, RY);
+  for (int v = 0; v < 10; ++v) li[v] = cb + node_off(t, v, RY, OO, RXP);
   tile_elem<T, KIND, MAP, R, t>(a, D, sx, sk, sy, li, m, bx0 + cx, by0 + cy, bz0 + cz);
 }
 
@@ -408,13 +424,14 @@ template <typename T, int KIND, int MAP, int TX, int TY, int TZ>
 __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_tile(TileArgs<T> a) {
   using Cfg = TileCfg<T, KIND, MAP, TX, TY, TZ>;
   constexpr int RX = Cfg::RX, RY = Cfg::RY, R = Cfg::R, NC = Cfg::NC, NTH = Cfg::NTH;
+  constexpr int OO = Cfg::OO, RXP = Cfg::RXP, RP = Cfg::RP;
   constexpr bool HASK = Cfg::HASK;
-  __shared__ T sx[NC][R];
+  __shared__ T sx[NC][RP];
   // the element results are accumulated in FP64 in both precisions: FP64
   // LDS atomics run at full speed on gfx950 where FP32 ones stall the LDS
   // pipeline, and the partial sums of a point keep 53-bit mantissas
-  __shared__ double sy[NC][R];
-  __shared__ T sk[HASK ? R : 1];
+  __shared__ double sy[NC][RP];
+  __shared__ T sk[HASK ? RP : 1];
 
   const int tid = threadIdx.x;
   const int nxcd = 8;
@@ -484,12 +501,14 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
   for (int p = 0; p < PF; ++p) {
     const int r = tid + p * NTH;
     if (r < R) {
+      const int row = r / RX, rx = r - row * RX;
+      const int sl = lds_slot(rx, row, OO, RXP);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        sx[c][r] = xv[p][c];
-        sy[c][r] = 0.0;
+        sx[c][sl] = xv[p][c];
+        sy[c][sl] = 0.0;
       }
-      if (HASK) sk[r] = kv[p];
+      if (HASK) sk[sl] = kv[p];
     }
   }
   __syncthreads();
@@ -499,12 +518,12 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
     // wavefront w applies type w to every cube
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     switch (w) {
-      case 0: type_loop<T, KIND, MAP, TX, TY, TZ, 0, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
-      case 1: type_loop<T, KIND, MAP, TX, TY, TZ, 1, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
-      case 2: type_loop<T, KIND, MAP, TX, TY, TZ, 2, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
-      case 3: type_loop<T, KIND, MAP, TX, TY, TZ, 3, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
-      case 4: type_loop<T, KIND, MAP, TX, TY, TZ, 4, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
-      default: type_loop<T, KIND, MAP, TX, TY, TZ, 5, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
+      case 0: type_loop<T, KIND, MAP, TX, TY, TZ, 0, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
+      case 1: type_loop<T, KIND, MAP, TX, TY, TZ, 1, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
+      case 2: type_loop<T, KIND, MAP, TX, TY, TZ, 2, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
+      case 3: type_loop<T, KIND, MAP, TX, TY, TZ, 3, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
+      case 4: type_loop<T, KIND, MAP, TX, TY, TZ, 4, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
+      default: type_loop<T, KIND, MAP, TX, TY, TZ, 5, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
     }
   } else {
     // slot e -> (type e / C, cube e % C); 64 | C makes the type wave-uniform
@@ -512,12 +531,12 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
     for (int e = tid; e < 6 * C; e += NTH) {
       const int t = __builtin_amdgcn_readfirstlane(e / C), c = e - t * C;
       switch (t) {
-        case 0: cube_elem<T, KIND, MAP, TX, TY, TZ, 0, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
-        case 1: cube_elem<T, KIND, MAP, TX, TY, TZ, 1, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
-        case 2: cube_elem<T, KIND, MAP, TX, TY, TZ, 2, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
-        case 3: cube_elem<T, KIND, MAP, TX, TY, TZ, 3, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
-        case 4: cube_elem<T, KIND, MAP, TX, TY, TZ, 4, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
-        default: cube_elem<T, KIND, MAP, TX, TY, TZ, 5, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
+        case 0: cube_elem<T, KIND, MAP, TX, TY, TZ, 0, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
+        case 1: cube_elem<T, KIND, MAP, TX, TY, TZ, 1, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
+        case 2: cube_elem<T, KIND, MAP, TX, TY, TZ, 2, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
+        case 3: cube_elem<T, KIND, MAP, TX, TY, TZ, 3, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
+        case 4: cube_elem<T, KIND, MAP, TX, TY, TZ, 4, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
+        default: cube_elem<T, KIND, MAP, TX, TY, TZ, 5, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
       }
     }
   }
@@ -532,12 +551,13 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
     if ((bnd >> zp) & 1u) continue;
     const bool excl = ((info >> 4) & 1) && ((rx & 1) || ((rx > 0 || bx0 == 0) && rx < 2 * TX));
     const int off = srb[row] + qi;
+    const int sl = lds_slot(rx, row, OO, RXP);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       if (excl)
-        yb[c][off] = T(sy[c][r]);
+        yb[c][off] = T(sy[c][sl]);
       else
-        atomicAdd(yb[c] + off, T(sy[c][r]));
+        atomicAdd(yb[c] + off, T(sy[c][sl]));
     }
   }
 }
