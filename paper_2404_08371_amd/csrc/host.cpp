@@ -478,12 +478,15 @@ tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const
   }
   if (st == TMF_OK) st = op->bnd.upload(mesh->bnd.data(), mesh->bnd.size());
   if (st == TMF_OK && space == 1) {
-    // the rows of the packed lattice cut into chunks of at most 64 points
+    // work units of the P1 row march: plane k, 62 points i0.., rows j0..j1-1
+    // (the rows of the plane with points at i >= i0), 8 rows per unit
     std::vector<int4> ch;
     const int N = S.N;
     for (int k = 0; k <= N; ++k)
-      for (int j = 0; j <= N - k; ++j)
-        for (int i0 = 0; i0 <= N - k - j; i0 += 64) ch.push_back(make_int4(j, k, i0, std::min(64, N - k - j - i0 + 1)));
+      for (int i0 = 0; i0 <= N - k; i0 += 62) {
+        const int jend = N - k - i0 + 1;
+        for (int j0 = 0; j0 < jend; j0 += 8) ch.push_back(make_int4(k, i0, j0, std::min(j0 + 8, jend)));
+      }
     op->nchunks = static_cast<int>(ch.size());
     st = op->chunks.upload(ch.data(), ch.size());
   }

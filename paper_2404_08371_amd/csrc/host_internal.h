@@ -83,7 +83,7 @@ struct tmf_op {
   int64_t ngroups = 0;
   DevBuf<uint8_t> owner;
   DevBuf<uint8_t> desc;  // one InstDesc of the op's precision
-  DevBuf<int4> chunks;   // P1: row chunks (j, k, i0, length) of one macro lattice
+  DevBuf<int4> chunks;   // P1: row-march work units (k, i0, j0, j1) of one macro lattice
   int nchunks = 0;
 };
 

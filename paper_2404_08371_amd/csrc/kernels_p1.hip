@@ -1,25 +1,30 @@
 // P1 operators: vertex-centric ("owner computes") matrix-free kernels.
 //
-// Each thread owns one lattice point p = (i, j, k) of one macro and forms row
-// p of A x: y_p = sum over the (up to 24) micro-tets T containing p of
+// Each lane owns one lattice point p = (i, j, k) of one macro and forms row p
+// of A x: y_p = sum over the (up to 24) micro-tets T containing p of
 // (A_T x_T)_p (equation (4.1) restricted to one row).  Every row is written
-// exactly once: no write conflicts, no atomics, fixed summation order.  A
-// wavefront owns a chunk of up to 64 consecutive points of one lattice row
-// (a host-built table lists the chunks, so no thread decodes a packed index),
-// the row bases of the 7 lattice rows its 15-point neighbourhoods touch are
-// computed once per wavefront, and all 15 neighbour loads of a point are
-// issued together (neighbouring lanes read neighbouring words).  Chunks at
-// distance >= 2 from every macro face (the bulk) take an unguarded path;
-// the others check each neighbour and zero Dirichlet DoFs of x (x_b ignored).
+// exactly once: no write conflicts, no atomics, fixed summation order.
+//
+// Data movement.  The 15-point neighbourhood of p spans 7 lattice rows: rows
+// j-1, j, j+1 of plane k, rows j, j+1 of plane k-1 and rows j-1, j of plane
+// k+1.  A wavefront owns 62 consecutive points of a row (lanes 1..62; lanes 0
+// and 63 hold the i-1 / i+1 neighbours of the ends) and marches along j
+// through a segment of rows of one plane, keeping a sliding window of rows
+// in registers: each step loads only the 3 rows that enter the window (one
+// per plane), issued one step ahead, and the i +- 1 neighbours come from the
+// adjacent lanes.  This takes the vector-memory request rate -- which bounds
+// a gather of 15 separate neighbour loads per point -- down to about 3.5 row
+// loads per point.  Rows are loaded with out-of-lattice points as 0 and, for
+// Dirichlet conditions, with boundary DoFs as 0 (x_b ignored), so every later
+// use of a row sees the masked values.
 //
 // The local matrices are the per-(macro, type) constants
 // Gp = |T| grad(lambda_a).grad(lambda_b) (affine macros: every micro-tet of
 // a type shares its Jacobian -- the loop-invariant hoisting of section
 // "Automatic Identification of Loop Invariants", done once on the host).
-// For the constant-coefficient operator they are pre-summed into 15-point
-// stencils, one per boundary class: which of the four macro faces (i = 0,
-// j = 0, k = 0, i + j + k = N) the point lies on decides which of its 24
-// micro-tets exist, so 16 stencils cover every point of a macro.
+// For the constant-coefficient operator, points inside the macro (all 24
+// micro-tets present) use their sum, a 15-point stencil; points on a macro
+// face (i = 0, j = 0, k = 0 or i + j + k = N) sum the micro-tets that exist.
 #include "tmf_internal.h"
 
 namespace tmf {
@@ -59,11 +64,14 @@ __device__ __forceinline__ T nbval(const T P[3][7], int q) {
   return P[kNbPlane[q]][kNbSlot[q]];
 }
 
+// per-type geometry: read-only, wave-uniform -> scalar loads via the constant address space
+template <typename T>
+using GeoPtr = const __attribute__((address_space(4))) TypeGeo<T> *;
+
 // row p of sum_T kbar_T Gp_T x_T over the existing micro-tets containing p
 template <typename T, int t, int a>
-__device__ __forceinline__ void p1k_tet(const TypeGeo<T> *__restrict__ g, const T X[3][7], const T K[3][7], int z,
-                                        T &acc) {
-  const T *G = g[t].Gp + 4 * a;
+__device__ __forceinline__ void p1k_tet(GeoPtr<T> g, const T X[3][7], const T K[3][7], int z, T &acc) {
+  const auto *G = g[t].Gp + 4 * a;
   const int q0 = kVS.v[t][a][0], q1 = kVS.v[t][a][1], q2 = kVS.v[t][a][2], q3 = kVS.v[t][a][3];
   const T r = G[0] * nbval(X, q0) + G[1] * nbval(X, q1) + G[2] * nbval(X, q2) + G[3] * nbval(X, q3);
   const T kb = (nbval(K, q0) + nbval(K, q1) + nbval(K, q2) + nbval(K, q3)) * T(0.25);
@@ -72,7 +80,7 @@ __device__ __forceinline__ void p1k_tet(const TypeGeo<T> *__restrict__ g, const 
 }
 
 template <typename T>
-__device__ __forceinline__ T p1k_row(const TypeGeo<T> *g, const T X[3][7], const T K[3][7], int z) {
+__device__ __forceinline__ T p1k_row(GeoPtr<T> g, const T X[3][7], const T K[3][7], int z) {
   T acc = T(0);
   p1k_tet<T, 0, 0>(g, X, K, z, acc); p1k_tet<T, 0, 1>(g, X, K, z, acc);
   p1k_tet<T, 0, 2>(g, X, K, z, acc); p1k_tet<T, 0, 3>(g, X, K, z, acc);
@@ -91,9 +99,8 @@ __device__ __forceinline__ T p1k_row(const TypeGeo<T> *g, const T X[3][7], const
 
 // 1/4 (D gy)_T . Gp_T (D x)_T summed over the existing micro-tets containing p
 template <typename T, int t, int a>
-__device__ __forceinline__ void kgrad_tet(const TypeGeo<T> *__restrict__ g, const T R[3][7], const T X[3][7], int z,
-                                          T &acc) {
-  const T *G = g[t].Gp;
+__device__ __forceinline__ void kgrad_tet(GeoPtr<T> g, const T R[3][7], const T X[3][7], int z, T &acc) {
+  const auto *G = g[t].Gp;
   T bil = T(0);
 #pragma unroll
   for (int c1 = 0; c1 < 4; ++c1) {
@@ -105,7 +112,7 @@ __device__ __forceinline__ void kgrad_tet(const TypeGeo<T> *__restrict__ g, cons
 }
 
 template <typename T>
-__device__ __forceinline__ T kgrad_row(const TypeGeo<T> *g, const T R[3][7], const T X[3][7], int z) {
+__device__ __forceinline__ T kgrad_row(GeoPtr<T> g, const T R[3][7], const T X[3][7], int z) {
   T acc = T(0);
   kgrad_tet<T, 0, 0>(g, R, X, z, acc); kgrad_tet<T, 0, 1>(g, R, X, z, acc);
   kgrad_tet<T, 0, 2>(g, R, X, z, acc); kgrad_tet<T, 0, 3>(g, R, X, z, acc);
@@ -122,173 +129,237 @@ __device__ __forceinline__ T kgrad_row(const TypeGeo<T> *g, const T R[3][7], con
   return acc * T(0.25);
 }
 
-// The 15-point neighbourhood of the points of one row chunk: row bases (in
-// the macro's block) of the 7 rows (j, k), (j+-1, k), (j, k+-1), (j+1, k-1),
-// (j-1, k+1); slot q of point (i, j, k) is at rb[row of q] + i + di(q).
-struct Rows {
-  int rb[3][3];  // [plane k-1, k, k+1][row j-1, j, j+1]
+// Row march.  Window of one field at step j (values at i = i0 - 1 + lane):
+//   c[0] = row (j-1, k), c[1] = (j, k), c[2] = (j+1, k)
+//   u[0] = row (j-1, k+1), u[1] = (j, k+1)
+//   d[0] = row (j, k-1), d[1] = (j+1, k-1)
+// Entering rows at step j+1: (j+2, k), (j+1, k+1), (j+2, k-1).
+template <typename T>
+struct Window {
+  T c[3], u[2], d[2];
 };
 
-__device__ __forceinline__ Rows chunk_rows(int j, int k, int N) {
-  Rows R;
-#pragma unroll
-  for (int p = 0; p < 3; ++p)
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const int kk = k + p - 1, jj = j + r - 1;
-      const int M = N - kk;
-      R.rb[p][r] = c3(N) - c3(M) + (jj * (2 * M + 3 - jj)) / 2;
-    }
-  return R;
+// the 15-point neighbourhood of each lane's point, in the slot layout of
+// kNbPlane / kNbSlot (in-plane offsets (0,0) (1,0) (-1,0) (0,1) (0,-1) (1,-1)
+// (-1,1)); i + 1 comes from lane + 1, i - 1 from lane - 1
+template <typename T>
+__device__ __forceinline__ void neighbourhood(const Window<T> &w, T P[3][7]) {
+  P[1][0] = w.c[1];
+  P[1][1] = __shfl_down(w.c[1], 1, 64);
+  P[1][2] = __shfl_up(w.c[1], 1, 64);
+  P[1][3] = w.c[2];
+  P[1][6] = __shfl_up(w.c[2], 1, 64);
+  P[1][4] = w.c[0];
+  P[1][5] = __shfl_down(w.c[0], 1, 64);
+  P[2][0] = w.u[1];
+  P[2][2] = __shfl_up(w.u[1], 1, 64);
+  P[2][4] = w.u[0];
+  P[2][5] = __shfl_down(w.u[0], 1, 64);
+  P[0][0] = w.d[0];
+  P[0][1] = __shfl_down(w.d[0], 1, 64);
+  P[0][3] = w.d[1];
+  P[0][6] = __shfl_up(w.d[1], 1, 64);
+  // slots no 15-point neighbour uses
+  P[2][1] = P[2][3] = P[2][6] = T(0);
+  P[0][2] = P[0][4] = P[0][5] = T(0);
 }
 
-// values of v at the neighbourhood of (i, j, k).  CHECK: points outside the
-// lattice read 0, and with MASK Dirichlet DoFs read 0 too.
-template <typename T, bool CHECK, bool MASK>
-__device__ __forceinline__ void gather15(const T *__restrict__ v, const Rows &R, int i, int j, int k, int N,
-                                         uint32_t bnd, T P[3][7]) {
-#pragma unroll
-  for (int q = 0; q < 15; ++q) {
-    const int di = kNb[q][0], dj = kNb[q][1], dk = kNb[q][2];
-    const int ii = i + di, jj = j + dj, kk = k + dk;
-    bool ok = true;
-    if (CHECK) {
-      ok = ii >= 0 && jj >= 0 && kk >= 0 && ii + jj + kk <= N;
-      if (MASK) ok = ok && !((bnd >> zero_pattern(ii, jj, kk, N)) & 1u);
-    }
-    T val = T(0);
-    if (ok) val = v[R.rb[dk + 1][dj + 1] + ii];
-    P[kNbPlane[q]][kNbSlot[q]] = val;
-  }
+// Loads of one lattice row (j, k) of one macro at i = i0 - 1 + lane: 0 outside
+// the lattice and, with MASK, at Dirichlet DoFs.  j and k are wave-uniform.
+template <typename T, bool MASK>
+__device__ __forceinline__ T row_load(const T *__restrict__ v, int i, int j, int k, int N, uint32_t dmask) {
+  if (j < 0 || k < 0 || j + k > N) return T(0);
+  const int lim = N - j - k;
+  if (i < 0 || i > lim) return T(0);
+  if (MASK && ((dmask >> zero_pattern(i, j, k, N)) & 1u)) return T(0);
+  return v[row_base(j, k, N) + i];
 }
 
-// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
-// Renumber them so that XCD x runs one contiguous run of the (macro, chunk
-// block) sequence, in order: neighbouring rows and planes -- the 15-point
-// neighbourhoods -- are then read through the same L2.
-__device__ __forceinline__ void xcd_block(int nchunks, int *m, int *cb) {
-  const int per_macro = (nchunks + 3) / 4;
+template <typename T, bool MASK>
+__device__ __forceinline__ void window_init(Window<T> &w, const T *v, int i, int j, int k, int N, uint32_t dm) {
+  w.c[0] = row_load<T, MASK>(v, i, j - 1, k, N, dm);
+  w.c[1] = row_load<T, MASK>(v, i, j, k, N, dm);
+  w.u[0] = row_load<T, MASK>(v, i, j - 1, k + 1, N, dm);
+  w.d[0] = row_load<T, MASK>(v, i, j, k - 1, N, dm);
+}
+// the three rows entering at step j
+template <typename T, bool MASK>
+__device__ __forceinline__ void window_next(T nx[3], const T *v, int i, int j, int k, int N, uint32_t dm) {
+  nx[0] = row_load<T, MASK>(v, i, j + 1, k, N, dm);
+  nx[1] = row_load<T, MASK>(v, i, j, k + 1, N, dm);
+  nx[2] = row_load<T, MASK>(v, i, j + 1, k - 1, N, dm);
+}
+template <typename T>
+__device__ __forceinline__ void window_enter(Window<T> &w, const T nx[3]) {
+  w.c[2] = nx[0];
+  w.u[1] = nx[1];
+  w.d[1] = nx[2];
+}
+template <typename T>
+__device__ __forceinline__ void window_slide(Window<T> &w) {
+  w.c[0] = w.c[1];
+  w.c[1] = w.c[2];
+  w.u[0] = w.u[1];
+  w.d[0] = w.d[1];
+}
+
+// Work unit (k, i0, j0, j1): rows j0 .. j1-1 of plane k, points i0 .. i0+61.
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2);
+// renumbered so that XCD x runs one contiguous run of the (macro, unit block)
+// sequence in order, neighbouring rows and planes meet in the same L2.
+struct Unit {
+  int m, k, i0, j0, j1;
+  bool valid;
+};
+__device__ __forceinline__ Unit unit_of(const int4 *__restrict__ units, int nunits) {
+  const int per_macro = (nunits + 3) / 4;
   const int nb = gridDim.x, b = blockIdx.x;
   const int x8 = b & 7, q = nb >> 3, rem = nb & 7;
   const int t = x8 * q + min(x8, rem) + (b >> 3);
-  *m = t / per_macro;
-  *cb = t - *m * per_macro;
+  Unit u;
+  u.m = t / per_macro;
+  const int id = __builtin_amdgcn_readfirstlane((t - u.m * per_macro) * 4 + (threadIdx.x >> 6));
+  u.valid = id < nunits;
+  const int4 w = units[u.valid ? id : 0];
+  u.k = __builtin_amdgcn_readfirstlane(w.x);
+  u.i0 = __builtin_amdgcn_readfirstlane(w.y);
+  u.j0 = __builtin_amdgcn_readfirstlane(w.z);
+  u.j1 = __builtin_amdgcn_readfirstlane(w.w);
+  return u;
 }
+constexpr int kUnitPoints = 62;  // output points per wavefront row
 
-// One wavefront per row chunk (up to 64 consecutive points of one lattice
-// row); a 1-D grid of ceil(chunks / 4) * macros workgroups of 4 wavefronts.
 template <typename T, int KIND>
-__global__ __launch_bounds__(256) void k_p1_apply(P1Args<T> a, const int4 *__restrict__ chunks, int nchunks) {
+__global__ __launch_bounds__(256) void k_p1_apply(P1Args<T> a, const int4 *__restrict__ units, int nunits) {
   constexpr bool VARK = KIND == P1_DIVKGRAD;
   const LatticeArgs<T> &L = a.lat;
-  const int N = L.N;
-  int m, cb;
-  xcd_block(nchunks, &m, &cb);
-  const int ch = cb * 4 + (threadIdx.x >> 6);
-  if (ch >= nchunks) return;
-  const int4 c = chunks[ch];  // j, k, i0, length
-  const int j = c.x, k = c.y, i = c.z + (threadIdx.x & 63);
-  if (i >= c.z + c.w) return;
-  const int64_t base = static_cast<int64_t>(m) * L.L;
-  const uint32_t bnd = L.bnd[m];
-  const Rows R = chunk_rows(j, k, N);
+  const Unit U = unit_of(units, nunits);
+  // the macro's 16 boundary-class stencils (all units of a workgroup share
+  // the macro); staged before any wavefront can leave
+  __shared__ T sw[VARK ? 1 : 16 * 15];
+  if (!VARK) {
+    for (int e = threadIdx.x; e < 16 * 15; e += 256) sw[e] = a.w15[16 * 15 * U.m + e];
+    __syncthreads();
+  }
+  if (!U.valid) return;
+  const int N = L.N, k = U.k, lane = threadIdx.x & 63, i = U.i0 - 1 + lane;
+  const int64_t base = static_cast<int64_t>(U.m) * L.L;
+  const uint32_t bnd = L.bnd[U.m];
+  const uint32_t dm = L.dirichlet ? bnd : 0u;
   const T *x = a.x + base;
   const T *kc = VARK ? a.k + base : nullptr;
-  const TypeGeo<T> *g = L.geo + 6 * m;
-  const int d = L.dirichlet ? 2 : 1;
-  // every point of the chunk at distance >= d from each macro face: all 24
-  // micro-tets exist and no neighbour is a Dirichlet DoF
-  const bool inner = j >= d && k >= d && c.z >= d && c.z + c.w - 1 + j + k <= N - d;
-  T X[3][7], K[3][7];
-  T acc = T(0);
-  if (inner) {
-    gather15<T, false, false>(x, R, i, j, k, N, bnd, X);
-    if (VARK) {
-      gather15<T, false, false>(kc, R, i, j, k, N, bnd, K);
-      acc = p1k_row(g, X, K, 0);
-    } else {
-      const T *w = a.w15 + 16 * 15 * m;  // class 0: the interior stencil
-#pragma unroll
-      for (int q = 0; q < 15; ++q) acc += w[q] * nbval(X, q);
-    }
-  } else {
-    const int z = zero_pattern(i, j, k, N);
-    if (!(L.dirichlet && ((bnd >> z) & 1u))) {
-      if (L.dirichlet)
-        gather15<T, true, true>(x, R, i, j, k, N, bnd, X);
-      else
-        gather15<T, true, false>(x, R, i, j, k, N, bnd, X);
-      if (VARK) {
-        gather15<T, true, false>(kc, R, i, j, k, N, bnd, K);
-        acc = p1k_row(g, X, K, z);
-      } else {
-        const T *w = a.w15 + (16 * m + z) * 15;
-#pragma unroll
-        for (int q = 0; q < 15; ++q) acc += w[q] * nbval(X, q);
-      }
-    }
+  T *y = a.y + base;
+  const GeoPtr<T> g = (GeoPtr<T>)(L.geo + 6 * U.m);
+  const bool out_lane = lane >= 1 && lane <= kUnitPoints;
+  // class-0 stencil (all 24 micro-tets present)
+  const auto *w0 = (const __attribute__((address_space(4))) T *)(a.w15 + 16 * 15 * U.m);
+
+  Window<T> X, K;
+  T nx[3], nk[3];
+  window_init<T, true>(X, x, i, U.j0, k, N, dm);
+  window_next<T, true>(nx, x, i, U.j0, k, N, dm);
+  if (VARK) {
+    window_init<T, false>(K, kc, i, U.j0, k, N, 0u);
+    window_next<T, false>(nk, kc, i, U.j0, k, N, 0u);
   }
-  a.y[base + R.rb[1][1] + i] = acc;
+  for (int j = U.j0; j < U.j1; ++j) {
+    window_enter(X, nx);
+    if (VARK) window_enter(K, nk);
+    if (j + 1 < U.j1) {  // the next step's rows, in flight during this step
+      window_next<T, true>(nx, x, i, j + 1, k, N, dm);
+      if (VARK) window_next<T, false>(nk, kc, i, j + 1, k, N, 0u);
+    }
+    T PX[3][7];
+    neighbourhood(X, PX);
+    const int z = zero_pattern(i, j, k, N);
+    const bool out = out_lane && i <= N - j - k;
+    T acc = T(0);
+    if (VARK) {
+      T PK[3][7];
+      neighbourhood(K, PK);
+      acc = p1k_row(g, PX, PK, z);
+    } else if (__ballot(out && z != 0) == 0) {
+      // every output point of the row segment lies inside the macro
+#pragma unroll
+      for (int q = 0; q < 15; ++q) acc += w0[q] * nbval(PX, q);
+    } else {
+      const T *w = sw + 15 * z;
+#pragma unroll
+      for (int q = 0; q < 15; ++q) acc += w[q] * nbval(PX, q);
+    }
+    if ((dm >> z) & 1u) acc = T(0);
+    if (out) y[row_base(j, k, N) + i] = acc;
+    window_slide(X);
+    if (VARK) window_slide(K);
+  }
 }
 
 // Fused reverse mode of the macro-local P1 div(k grad) apply:
 //   gx_p = (L(k) gy)_p,  gk_p = sum_{T containing p} 1/4 (D gy)_T . Gp_T (D x)_T
 template <typename T>
-__global__ __launch_bounds__(256) void k_p1_adjoint(P1AdjArgs<T> a, const int4 *__restrict__ chunks, int nchunks) {
+__global__ __launch_bounds__(256) void k_p1_adjoint(P1AdjArgs<T> a, const int4 *__restrict__ units, int nunits) {
   const LatticeArgs<T> &L = a.lat;
-  const int N = L.N;
-  int m, cb;
-  xcd_block(nchunks, &m, &cb);
-  const int ch = cb * 4 + (threadIdx.x >> 6);
-  if (ch >= nchunks) return;
-  const int4 c = chunks[ch];
-  const int j = c.x, k = c.y, i = c.z + (threadIdx.x & 63);
-  if (i >= c.z + c.w) return;
-  const int64_t base = static_cast<int64_t>(m) * L.L;
-  const uint32_t bnd = L.bnd[m];
-  const Rows R = chunk_rows(j, k, N);
-  const TypeGeo<T> *g = L.geo + 6 * m;
-  const int d = L.dirichlet ? 2 : 1;
-  const bool inner = j >= d && k >= d && c.z >= d && c.z + c.w - 1 + j + k <= N - d;
-  T G[3][7], X[3][7], K[3][7];
-  int z = 0;
-  if (inner) {
-    gather15<T, false, false>(a.gy + base, R, i, j, k, N, bnd, G);
-    gather15<T, false, false>(a.x + base, R, i, j, k, N, bnd, X);
-    gather15<T, false, false>(a.k + base, R, i, j, k, N, bnd, K);
-  } else {
-    z = zero_pattern(i, j, k, N);
-    if (L.dirichlet) {
-      gather15<T, true, true>(a.gy + base, R, i, j, k, N, bnd, G);
-      gather15<T, true, true>(a.x + base, R, i, j, k, N, bnd, X);
-    } else {
-      gather15<T, true, false>(a.gy + base, R, i, j, k, N, bnd, G);
-      gather15<T, true, false>(a.x + base, R, i, j, k, N, bnd, X);
+  const Unit U = unit_of(units, nunits);
+  if (!U.valid) return;
+  const int N = L.N, k = U.k, lane = threadIdx.x & 63, i = U.i0 - 1 + lane;
+  const int64_t base = static_cast<int64_t>(U.m) * L.L;
+  const uint32_t bnd = L.bnd[U.m];
+  const uint32_t dm = L.dirichlet ? bnd : 0u;
+  const T *gy = a.gy + base, *x = a.x + base, *kc = a.k + base;
+  const GeoPtr<T> g = (GeoPtr<T>)(L.geo + 6 * U.m);
+  const bool out_lane = lane >= 1 && lane <= kUnitPoints;
+
+  Window<T> G, X, K;
+  T ng[3], nx[3], nk[3];
+  window_init<T, true>(G, gy, i, U.j0, k, N, dm);
+  window_init<T, true>(X, x, i, U.j0, k, N, dm);
+  window_init<T, false>(K, kc, i, U.j0, k, N, 0u);
+  window_next<T, true>(ng, gy, i, U.j0, k, N, dm);
+  window_next<T, true>(nx, x, i, U.j0, k, N, dm);
+  window_next<T, false>(nk, kc, i, U.j0, k, N, 0u);
+  for (int j = U.j0; j < U.j1; ++j) {
+    window_enter(G, ng);
+    window_enter(X, nx);
+    window_enter(K, nk);
+    if (j + 1 < U.j1) {
+      window_next<T, true>(ng, gy, i, j + 1, k, N, dm);
+      window_next<T, true>(nx, x, i, j + 1, k, N, dm);
+      window_next<T, false>(nk, kc, i, j + 1, k, N, 0u);
     }
-    gather15<T, true, false>(a.k + base, R, i, j, k, N, bnd, K);
+    T PG[3][7], PX[3][7], PK[3][7];
+    neighbourhood(G, PG);
+    neighbourhood(X, PX);
+    neighbourhood(K, PK);
+    const int z = zero_pattern(i, j, k, N);
+    const T gx = ((dm >> z) & 1u) ? T(0) : p1k_row(g, PG, PK, z);
+    const T gk = kgrad_row(g, PG, PX, z);
+    if (out_lane && i <= N - j - k) {
+      const int64_t slot = base + row_base(j, k, N) + i;
+      a.gx[slot] = gx;
+      if (a.gk) a.gk[slot] = gk;
+    }
+    window_slide(G);
+    window_slide(X);
+    window_slide(K);
   }
-  const bool self_bnd = L.dirichlet && ((bnd >> z) & 1u);
-  const int64_t slot = base + R.rb[1][1] + i;
-  a.gx[slot] = self_bnd ? T(0) : p1k_row(g, G, K, z);
-  if (a.gk) a.gk[slot] = kgrad_row(g, G, X, z);
 }
 
 }  // namespace
 
 template <typename T>
-hipError_t launch_p1_apply(const P1Args<T> &a, int kind, const int4 *chunks, int nchunks, hipStream_t s) {
-  const dim3 grid(((nchunks + 3) / 4) * a.lat.nt);
+hipError_t launch_p1_apply(const P1Args<T> &a, int kind, const int4 *units, int nunits, hipStream_t s) {
+  const dim3 grid(((nunits + 3) / 4) * a.lat.nt);
   if (kind == P1_LAPLACE)
-    hipLaunchKernelGGL((k_p1_apply<T, P1_LAPLACE>), grid, dim3(256), 0, s, a, chunks, nchunks);
+    hipLaunchKernelGGL((k_p1_apply<T, P1_LAPLACE>), grid, dim3(256), 0, s, a, units, nunits);
   else
-    hipLaunchKernelGGL((k_p1_apply<T, P1_DIVKGRAD>), grid, dim3(256), 0, s, a, chunks, nchunks);
+    hipLaunchKernelGGL((k_p1_apply<T, P1_DIVKGRAD>), grid, dim3(256), 0, s, a, units, nunits);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_p1_adjoint(const P1AdjArgs<T> &a, const int4 *chunks, int nchunks, hipStream_t s) {
-  const dim3 grid(((nchunks + 3) / 4) * a.lat.nt);
-  hipLaunchKernelGGL((k_p1_adjoint<T>), grid, dim3(256), 0, s, a, chunks, nchunks);
+hipError_t launch_p1_adjoint(const P1AdjArgs<T> &a, const int4 *units, int nunits, hipStream_t s) {
+  const dim3 grid(((nunits + 3) / 4) * a.lat.nt);
+  hipLaunchKernelGGL((k_p1_adjoint<T>), grid, dim3(256), 0, s, a, units, nunits);
   return hipGetLastError();
 }
 
