@@ -68,12 +68,36 @@ __device__ __forceinline__ T nbval(const T P[3][7], int q) {
 template <typename T>
 using GeoPtr = const __attribute__((address_space(4))) TypeGeo<T> *;
 
+// Gp_T is symmetric with zero row sums (sum_b grad(lambda_b) = 0), so its six
+// off-diagonal entries determine it; the element code reads only those (upper
+// triangle: 36 values per macro, which stay in scalar registers) and works
+// with differences to the centre point p:
+//   (Gp x)_a = sum_{c != a} Gp_ac (x_c - x_a)
+//   r^T Gp x = -sum_{a < c} Gp_ac (r_a - r_c)(x_a - x_c)
+template <typename T>
+__device__ __forceinline__ T goff(GeoPtr<T> g, int t, int a, int c) {
+  return a < c ? g[t].Gp[4 * a + c] : g[t].Gp[4 * c + a];
+}
+
+// neighbour values minus the centre value (slot 0 is p itself)
+template <typename T>
+__device__ __forceinline__ void centred(const T P[3][7], T D[3][7]) {
+  const T c = P[1][0];
+#pragma unroll
+  for (int pl = 0; pl < 3; ++pl)
+#pragma unroll
+    for (int sl = 0; sl < 7; ++sl) D[pl][sl] = P[pl][sl] - c;
+}
+
 // row p of sum_T kbar_T Gp_T x_T over the existing micro-tets containing p
+// (p is local vertex a of the type-t micro-tet; DX = centred x)
 template <typename T, int t, int a>
-__device__ __forceinline__ void p1k_tet(GeoPtr<T> g, const T X[3][7], const T K[3][7], int z, T &acc) {
-  const auto *G = g[t].Gp + 4 * a;
+__device__ __forceinline__ void p1k_tet(GeoPtr<T> g, const T DX[3][7], const T K[3][7], int z, T &acc) {
+  T r = T(0);
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if (c != a) r += goff(g, t, a, c) * nbval(DX, kVS.v[t][a][c]);
   const int q0 = kVS.v[t][a][0], q1 = kVS.v[t][a][1], q2 = kVS.v[t][a][2], q3 = kVS.v[t][a][3];
-  const T r = G[0] * nbval(X, q0) + G[1] * nbval(X, q1) + G[2] * nbval(X, q2) + G[3] * nbval(X, q3);
   const T kb = (nbval(K, q0) + nbval(K, q1) + nbval(K, q2) + nbval(K, q3)) * T(0.25);
   const T c = kb * r;
   acc += tet_exists<t, a>(z) ? c : T(0);
@@ -81,51 +105,57 @@ __device__ __forceinline__ void p1k_tet(GeoPtr<T> g, const T X[3][7], const T K[
 
 template <typename T>
 __device__ __forceinline__ T p1k_row(GeoPtr<T> g, const T X[3][7], const T K[3][7], int z) {
+  T DX[3][7];
+  centred(X, DX);
   T acc = T(0);
-  p1k_tet<T, 0, 0>(g, X, K, z, acc); p1k_tet<T, 0, 1>(g, X, K, z, acc);
-  p1k_tet<T, 0, 2>(g, X, K, z, acc); p1k_tet<T, 0, 3>(g, X, K, z, acc);
-  p1k_tet<T, 1, 0>(g, X, K, z, acc); p1k_tet<T, 1, 1>(g, X, K, z, acc);
-  p1k_tet<T, 1, 2>(g, X, K, z, acc); p1k_tet<T, 1, 3>(g, X, K, z, acc);
-  p1k_tet<T, 2, 0>(g, X, K, z, acc); p1k_tet<T, 2, 1>(g, X, K, z, acc);
-  p1k_tet<T, 2, 2>(g, X, K, z, acc); p1k_tet<T, 2, 3>(g, X, K, z, acc);
-  p1k_tet<T, 3, 0>(g, X, K, z, acc); p1k_tet<T, 3, 1>(g, X, K, z, acc);
-  p1k_tet<T, 3, 2>(g, X, K, z, acc); p1k_tet<T, 3, 3>(g, X, K, z, acc);
-  p1k_tet<T, 4, 0>(g, X, K, z, acc); p1k_tet<T, 4, 1>(g, X, K, z, acc);
-  p1k_tet<T, 4, 2>(g, X, K, z, acc); p1k_tet<T, 4, 3>(g, X, K, z, acc);
-  p1k_tet<T, 5, 0>(g, X, K, z, acc); p1k_tet<T, 5, 1>(g, X, K, z, acc);
-  p1k_tet<T, 5, 2>(g, X, K, z, acc); p1k_tet<T, 5, 3>(g, X, K, z, acc);
+  p1k_tet<T, 0, 0>(g, DX, K, z, acc); p1k_tet<T, 0, 1>(g, DX, K, z, acc);
+  p1k_tet<T, 0, 2>(g, DX, K, z, acc); p1k_tet<T, 0, 3>(g, DX, K, z, acc);
+  p1k_tet<T, 1, 0>(g, DX, K, z, acc); p1k_tet<T, 1, 1>(g, DX, K, z, acc);
+  p1k_tet<T, 1, 2>(g, DX, K, z, acc); p1k_tet<T, 1, 3>(g, DX, K, z, acc);
+  p1k_tet<T, 2, 0>(g, DX, K, z, acc); p1k_tet<T, 2, 1>(g, DX, K, z, acc);
+  p1k_tet<T, 2, 2>(g, DX, K, z, acc); p1k_tet<T, 2, 3>(g, DX, K, z, acc);
+  p1k_tet<T, 3, 0>(g, DX, K, z, acc); p1k_tet<T, 3, 1>(g, DX, K, z, acc);
+  p1k_tet<T, 3, 2>(g, DX, K, z, acc); p1k_tet<T, 3, 3>(g, DX, K, z, acc);
+  p1k_tet<T, 4, 0>(g, DX, K, z, acc); p1k_tet<T, 4, 1>(g, DX, K, z, acc);
+  p1k_tet<T, 4, 2>(g, DX, K, z, acc); p1k_tet<T, 4, 3>(g, DX, K, z, acc);
+  p1k_tet<T, 5, 0>(g, DX, K, z, acc); p1k_tet<T, 5, 1>(g, DX, K, z, acc);
+  p1k_tet<T, 5, 2>(g, DX, K, z, acc); p1k_tet<T, 5, 3>(g, DX, K, z, acc);
   return acc;
 }
 
 // 1/4 (D gy)_T . Gp_T (D x)_T summed over the existing micro-tets containing p
+// (DR, DX centred gy and x)
 template <typename T, int t, int a>
-__device__ __forceinline__ void kgrad_tet(GeoPtr<T> g, const T R[3][7], const T X[3][7], int z, T &acc) {
-  const auto *G = g[t].Gp;
+__device__ __forceinline__ void kgrad_tet(GeoPtr<T> g, const T DR[3][7], const T DX[3][7], int z, T &acc) {
   T bil = T(0);
 #pragma unroll
-  for (int c1 = 0; c1 < 4; ++c1) {
-    const T row = G[4 * c1 + 0] * nbval(X, kVS.v[t][a][0]) + G[4 * c1 + 1] * nbval(X, kVS.v[t][a][1]) +
-                  G[4 * c1 + 2] * nbval(X, kVS.v[t][a][2]) + G[4 * c1 + 3] * nbval(X, kVS.v[t][a][3]);
-    bil += nbval(R, kVS.v[t][a][c1]) * row;
-  }
+  for (int c1 = 0; c1 < 4; ++c1)
+#pragma unroll
+    for (int c2 = c1 + 1; c2 < 4; ++c2) {
+      const int q1 = kVS.v[t][a][c1], q2 = kVS.v[t][a][c2];
+      bil -= goff(g, t, c1, c2) * (nbval(DR, q1) - nbval(DR, q2)) * (nbval(DX, q1) - nbval(DX, q2));
+    }
   acc += tet_exists<t, a>(z) ? bil : T(0);
 }
 
 template <typename T>
 __device__ __forceinline__ T kgrad_row(GeoPtr<T> g, const T R[3][7], const T X[3][7], int z) {
+  T DR[3][7], DX[3][7];
+  centred(R, DR);
+  centred(X, DX);
   T acc = T(0);
-  kgrad_tet<T, 0, 0>(g, R, X, z, acc); kgrad_tet<T, 0, 1>(g, R, X, z, acc);
-  kgrad_tet<T, 0, 2>(g, R, X, z, acc); kgrad_tet<T, 0, 3>(g, R, X, z, acc);
-  kgrad_tet<T, 1, 0>(g, R, X, z, acc); kgrad_tet<T, 1, 1>(g, R, X, z, acc);
-  kgrad_tet<T, 1, 2>(g, R, X, z, acc); kgrad_tet<T, 1, 3>(g, R, X, z, acc);
-  kgrad_tet<T, 2, 0>(g, R, X, z, acc); kgrad_tet<T, 2, 1>(g, R, X, z, acc);
-  kgrad_tet<T, 2, 2>(g, R, X, z, acc); kgrad_tet<T, 2, 3>(g, R, X, z, acc);
-  kgrad_tet<T, 3, 0>(g, R, X, z, acc); kgrad_tet<T, 3, 1>(g, R, X, z, acc);
-  kgrad_tet<T, 3, 2>(g, R, X, z, acc); kgrad_tet<T, 3, 3>(g, R, X, z, acc);
-  kgrad_tet<T, 4, 0>(g, R, X, z, acc); kgrad_tet<T, 4, 1>(g, R, X, z, acc);
-  kgrad_tet<T, 4, 2>(g, R, X, z, acc); kgrad_tet<T, 4, 3>(g, R, X, z, acc);
-  kgrad_tet<T, 5, 0>(g, R, X, z, acc); kgrad_tet<T, 5, 1>(g, R, X, z, acc);
-  kgrad_tet<T, 5, 2>(g, R, X, z, acc); kgrad_tet<T, 5, 3>(g, R, X, z, acc);
+  kgrad_tet<T, 0, 0>(g, DR, DX, z, acc); kgrad_tet<T, 0, 1>(g, DR, DX, z, acc);
+  kgrad_tet<T, 0, 2>(g, DR, DX, z, acc); kgrad_tet<T, 0, 3>(g, DR, DX, z, acc);
+  kgrad_tet<T, 1, 0>(g, DR, DX, z, acc); kgrad_tet<T, 1, 1>(g, DR, DX, z, acc);
+  kgrad_tet<T, 1, 2>(g, DR, DX, z, acc); kgrad_tet<T, 1, 3>(g, DR, DX, z, acc);
+  kgrad_tet<T, 2, 0>(g, DR, DX, z, acc); kgrad_tet<T, 2, 1>(g, DR, DX, z, acc);
+  kgrad_tet<T, 2, 2>(g, DR, DX, z, acc); kgrad_tet<T, 2, 3>(g, DR, DX, z, acc);
+  kgrad_tet<T, 3, 0>(g, DR, DX, z, acc); kgrad_tet<T, 3, 1>(g, DR, DX, z, acc);
+  kgrad_tet<T, 3, 2>(g, DR, DX, z, acc); kgrad_tet<T, 3, 3>(g, DR, DX, z, acc);
+  kgrad_tet<T, 4, 0>(g, DR, DX, z, acc); kgrad_tet<T, 4, 1>(g, DR, DX, z, acc);
+  kgrad_tet<T, 4, 2>(g, DR, DX, z, acc); kgrad_tet<T, 4, 3>(g, DR, DX, z, acc);
+  kgrad_tet<T, 5, 0>(g, DR, DX, z, acc); kgrad_tet<T, 5, 1>(g, DR, DX, z, acc);
+  kgrad_tet<T, 5, 2>(g, DR, DX, z, acc); kgrad_tet<T, 5, 3>(g, DR, DX, z, acc);
   return acc * T(0.25);
 }
 
@@ -164,19 +194,49 @@ __device__ __forceinline__ void neighbourhood(const Window<T> &w, T P[3][7]) {
   P[0][2] = P[0][4] = P[0][5] = T(0);
 }
 
+// Buffer resources over one macro block.  The hardware range check of buffer
+// instructions turns an access at an offset past the block into a load of 0
+// or a dropped store, so out-of-lattice lanes need no branch: every step issues
+// the same loads and stores, and the wait for rows prefetched two steps earlier
+// can leave the newer loads in flight.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kFar = 0x7fffff00;  // byte offset past any block (blocks are < 2^31 bytes)
+template <typename T>
+__device__ __forceinline__ Rsrc block_rsrc(const T *p, int points) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(p), 0, points * static_cast<int>(sizeof(T)), 0x00020000);
+}
+__device__ __forceinline__ double buf_load(double, Rsrc r, int off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ float buf_load(float, Rsrc r, int off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+typedef unsigned int U32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void buf_store(double v, Rsrc r, int off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(float v, Rsrc r, int off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+}
+// byte offset of point (i, j, k) of the block, or kFar if `ok` is false
+template <typename T>
+__device__ __forceinline__ int point_off(bool ok, int i, int j, int k, int N) {
+  return ok ? (row_base(j, k, N) + i) * static_cast<int>(sizeof(T)) : kFar;
+}
+
 // Loads of one lattice row (j, k) of one macro at i = i0 - 1 + lane: 0 outside
 // the lattice and, with MASK, at Dirichlet DoFs.  j and k are wave-uniform.
 template <typename T, bool MASK>
-__device__ __forceinline__ T row_load(const T *__restrict__ v, int i, int j, int k, int N, uint32_t dmask) {
-  if (j < 0 || k < 0 || j + k > N) return T(0);
+__device__ __forceinline__ T row_load(Rsrc v, int i, int j, int k, int N, uint32_t dmask) {
+  const bool row_ok = j >= 0 && k >= 0 && j + k <= N;
   const int lim = N - j - k;
-  if (i < 0 || i > lim) return T(0);
-  if (MASK && ((dmask >> zero_pattern(i, j, k, N)) & 1u)) return T(0);
-  return v[row_base(j, k, N) + i];
+  bool ok = row_ok && i >= 0 && i <= lim;
+  if (MASK) ok = ok && !((dmask >> ((i == lim) | ((i == 0) << 1) | ((j == 0) << 2) | ((k == 0) << 3))) & 1u);
+  return buf_load(T(0), v, point_off<T>(ok, i, j, k, N));
 }
 
 template <typename T, bool MASK>
-__device__ __forceinline__ void window_init(Window<T> &w, const T *v, int i, int j, int k, int N, uint32_t dm) {
+__device__ __forceinline__ void window_init(Window<T> &w, Rsrc v, int i, int j, int k, int N, uint32_t dm) {
   w.c[0] = row_load<T, MASK>(v, i, j - 1, k, N, dm);
   w.c[1] = row_load<T, MASK>(v, i, j, k, N, dm);
   w.u[0] = row_load<T, MASK>(v, i, j - 1, k + 1, N, dm);
@@ -184,7 +244,7 @@ __device__ __forceinline__ void window_init(Window<T> &w, const T *v, int i, int
 }
 // the three rows entering at step j
 template <typename T, bool MASK>
-__device__ __forceinline__ void window_next(T nx[3], const T *v, int i, int j, int k, int N, uint32_t dm) {
+__device__ __forceinline__ void window_next(T nx[3], Rsrc v, int i, int j, int k, int N, uint32_t dm) {
   nx[0] = row_load<T, MASK>(v, i, j + 1, k, N, dm);
   nx[1] = row_load<T, MASK>(v, i, j, k + 1, N, dm);
   nx[2] = row_load<T, MASK>(v, i, j + 1, k - 1, N, dm);
@@ -246,29 +306,34 @@ __global__ __launch_bounds__(256) void k_p1_apply(P1Args<T> a, const int4 *__res
   const int64_t base = static_cast<int64_t>(U.m) * L.L;
   const uint32_t bnd = L.bnd[U.m];
   const uint32_t dm = L.dirichlet ? bnd : 0u;
-  const T *x = a.x + base;
-  const T *kc = VARK ? a.k + base : nullptr;
-  T *y = a.y + base;
+  const Rsrc x = block_rsrc(a.x + base, L.L);
+  const Rsrc kc = block_rsrc(VARK ? a.k + base : a.x + base, VARK ? L.L : 0);
+  const Rsrc y = block_rsrc(a.y + base, L.L);
   const GeoPtr<T> g = (GeoPtr<T>)(L.geo + 6 * U.m);
   const bool out_lane = lane >= 1 && lane <= kUnitPoints;
   // class-0 stencil (all 24 micro-tets present)
   const auto *w0 = (const __attribute__((address_space(4))) T *)(a.w15 + 16 * 15 * U.m);
 
+  // rows entering at step j were loaded at step j - PD.  With PD = 2 the two
+  // prefetch buffers alternate between even and odd steps (loads are always
+  // issued; past the segment end they read masked zeros), so the wait for one
+  // buffer leaves the other's loads in flight.  The variable-coefficient form
+  // keeps PD = 1: its second field and element code need the registers.
+  constexpr int PD = VARK ? 1 : 2;
   Window<T> X, K;
-  T nx[3], nk[3];
+  T nx[PD][3], nk[PD][3];
   window_init<T, true>(X, x, i, U.j0, k, N, dm);
-  window_next<T, true>(nx, x, i, U.j0, k, N, dm);
-  if (VARK) {
-    window_init<T, false>(K, kc, i, U.j0, k, N, 0u);
-    window_next<T, false>(nk, kc, i, U.j0, k, N, 0u);
+  if (VARK) window_init<T, false>(K, kc, i, U.j0, k, N, 0u);
+#pragma unroll
+  for (int b = 0; b < PD; ++b) {
+    window_next<T, true>(nx[b], x, i, U.j0 + b, k, N, dm);
+    if (VARK) window_next<T, false>(nk[b], kc, i, U.j0 + b, k, N, 0u);
   }
-  for (int j = U.j0; j < U.j1; ++j) {
-    window_enter(X, nx);
-    if (VARK) window_enter(K, nk);
-    if (j + 1 < U.j1) {  // the next step's rows, in flight during this step
-      window_next<T, true>(nx, x, i, j + 1, k, N, dm);
-      if (VARK) window_next<T, false>(nk, kc, i, j + 1, k, N, 0u);
-    }
+  auto step = [&](int j, T(&nxb)[3], T(&nkb)[3]) {
+    window_enter(X, nxb);
+    if (VARK) window_enter(K, nkb);
+    window_next<T, true>(nxb, x, i, j + PD, k, N, dm);
+    if (VARK) window_next<T, false>(nkb, kc, i, j + PD, k, N, 0u);
     T PX[3][7];
     neighbourhood(X, PX);
     const int z = zero_pattern(i, j, k, N);
@@ -288,9 +353,13 @@ __global__ __launch_bounds__(256) void k_p1_apply(P1Args<T> a, const int4 *__res
       for (int q = 0; q < 15; ++q) acc += w[q] * nbval(PX, q);
     }
     if ((dm >> z) & 1u) acc = T(0);
-    if (out) y[row_base(j, k, N) + i] = acc;
+    buf_store(acc, y, point_off<T>(out, i, j, k, N));
     window_slide(X);
     if (VARK) window_slide(K);
+  };
+  for (int j = U.j0; j < U.j1; j += PD) {
+    step(j, nx[0], nk[0]);
+    if (PD == 2 && j + 1 < U.j1) step(j + 1, nx[PD - 1], nk[PD - 1]);
   }
 }
 
@@ -305,10 +374,13 @@ __global__ __launch_bounds__(256) void k_p1_adjoint(P1AdjArgs<T> a, const int4 *
   const int64_t base = static_cast<int64_t>(U.m) * L.L;
   const uint32_t bnd = L.bnd[U.m];
   const uint32_t dm = L.dirichlet ? bnd : 0u;
-  const T *gy = a.gy + base, *x = a.x + base, *kc = a.k + base;
+  const Rsrc gy = block_rsrc(a.gy + base, L.L), x = block_rsrc(a.x + base, L.L), kc = block_rsrc(a.k + base, L.L);
+  const Rsrc gxr = block_rsrc(a.gx + base, L.L);
+  const Rsrc gkr = block_rsrc(a.gk ? a.gk + base : a.gx + base, a.gk ? L.L : 0);  // no gk: every store dropped
   const GeoPtr<T> g = (GeoPtr<T>)(L.geo + 6 * U.m);
   const bool out_lane = lane >= 1 && lane <= kUnitPoints;
 
+  // three fields: rows entering at step j are loaded at step j - 1
   Window<T> G, X, K;
   T ng[3], nx[3], nk[3];
   window_init<T, true>(G, gy, i, U.j0, k, N, dm);
@@ -321,11 +393,9 @@ __global__ __launch_bounds__(256) void k_p1_adjoint(P1AdjArgs<T> a, const int4 *
     window_enter(G, ng);
     window_enter(X, nx);
     window_enter(K, nk);
-    if (j + 1 < U.j1) {
-      window_next<T, true>(ng, gy, i, j + 1, k, N, dm);
-      window_next<T, true>(nx, x, i, j + 1, k, N, dm);
-      window_next<T, false>(nk, kc, i, j + 1, k, N, 0u);
-    }
+    window_next<T, true>(ng, gy, i, j + 1, k, N, dm);
+    window_next<T, true>(nx, x, i, j + 1, k, N, dm);
+    window_next<T, false>(nk, kc, i, j + 1, k, N, 0u);
     T PG[3][7], PX[3][7], PK[3][7];
     neighbourhood(G, PG);
     neighbourhood(X, PX);
@@ -333,11 +403,9 @@ __global__ __launch_bounds__(256) void k_p1_adjoint(P1AdjArgs<T> a, const int4 *
     const int z = zero_pattern(i, j, k, N);
     const T gx = ((dm >> z) & 1u) ? T(0) : p1k_row(g, PG, PK, z);
     const T gk = kgrad_row(g, PG, PX, z);
-    if (out_lane && i <= N - j - k) {
-      const int64_t slot = base + row_base(j, k, N) + i;
-      a.gx[slot] = gx;
-      if (a.gk) a.gk[slot] = gk;
-    }
+    const int off = point_off<T>(out_lane && i <= N - j - k, i, j, k, N);
+    buf_store(gx, gxr, off);
+    buf_store(gk, gkr, off);
     window_slide(G);
     window_slide(X);
     window_slide(K);
