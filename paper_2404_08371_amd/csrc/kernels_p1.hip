@@ -363,6 +363,83 @@ __global__ __launch_bounds__(256) void k_p1_apply(P1Args<T> a, const int4 *__res
   }
 }
 
+// Constant-coefficient stencil, 2.5-D blocking: a wavefront owns a tile of
+// KJ rows x 62 points (rows j0 .. j0+KJ-1, points i0 .. i0+61) and marches
+// through planes k0 .. k1-1.  It holds plane k's rows j0-1 .. j0+KJ, plane
+// k-1's rows j0 .. j0+KJ and plane k+1's rows j0-1 .. j0+KJ-1; a step to
+// plane k+1 loads KJ + 2 rows (plane k+2's KJ + 1, plane k+1's row j0+KJ)
+// for KJ output rows, issued one step ahead.
+constexpr int KJ = 4;
+template <typename T>
+__global__ __launch_bounds__(256) void k_p1_stencil(P1Args<T> a, const int4 *__restrict__ units, int nunits) {
+  const LatticeArgs<T> &L = a.lat;
+  const Unit U0 = unit_of(units, nunits);
+  __shared__ T sw[16 * 15];
+  for (int e = threadIdx.x; e < 16 * 15; e += 256) sw[e] = a.w15[16 * 15 * U0.m + e];
+  __syncthreads();
+  if (!U0.valid) return;
+  // unit fields: (j0, i0, k0, k1)
+  const int j0 = U0.k, i0 = U0.i0, k0 = U0.j0, k1 = U0.j1;
+  const int N = L.N, lane = threadIdx.x & 63, i = i0 - 1 + lane;
+  const int64_t base = static_cast<int64_t>(U0.m) * L.L;
+  const uint32_t dm = L.dirichlet ? L.bnd[U0.m] : 0u;
+  const Rsrc x = block_rsrc(a.x + base, L.L);
+  const Rsrc y = block_rsrc(a.y + base, L.L);
+  const bool out_lane = lane >= 1 && lane <= kUnitPoints;
+  const auto *w0 = (const __attribute__((address_space(4))) T *)(a.w15 + 16 * 15 * U0.m);
+
+  T A[KJ + 2], B[KJ + 1], C[KJ + 1];  // plane k rows j0-1.., plane k-1 rows j0.., plane k+1 rows j0-1..
+  T nC[KJ + 1], nA;                   // next step: plane k+2 rows j0-1.., plane k+1 row j0+KJ
+#pragma unroll
+  for (int r = 0; r < KJ + 2; ++r) A[r] = row_load<T, true>(x, i, j0 - 1 + r, k0, N, dm);
+#pragma unroll
+  for (int r = 0; r < KJ + 1; ++r) {
+    B[r] = row_load<T, true>(x, i, j0 + r, k0 - 1, N, dm);
+    C[r] = row_load<T, true>(x, i, j0 - 1 + r, k0 + 1, N, dm);
+  }
+  for (int k = k0; k < k1; ++k) {
+    // plane k+1's missing row and plane k+2, in flight during this step
+    nA = row_load<T, true>(x, i, j0 + KJ, k + 1, N, dm);
+#pragma unroll
+    for (int r = 0; r < KJ + 1; ++r) nC[r] = row_load<T, true>(x, i, j0 - 1 + r, k + 2, N, dm);
+#pragma unroll
+    for (int r = 0; r < KJ; ++r) {
+      const int j = j0 + r;
+      Window<T> w;
+      w.c[0] = A[r];
+      w.c[1] = A[r + 1];
+      w.c[2] = A[r + 2];
+      w.d[0] = B[r];
+      w.d[1] = B[r + 1];
+      w.u[0] = C[r];
+      w.u[1] = C[r + 1];
+      T P[3][7];
+      neighbourhood(w, P);
+      const int z = zero_pattern(i, j, k, N);
+      const bool out = out_lane && i <= N - j - k;
+      T acc = T(0);
+      if (__ballot(out && z != 0) == 0) {
+#pragma unroll
+        for (int q = 0; q < 15; ++q) acc += w0[q] * nbval(P, q);
+      } else {
+        const T *wz = sw + 15 * z;
+#pragma unroll
+        for (int q = 0; q < 15; ++q) acc += wz[q] * nbval(P, q);
+      }
+      if ((dm >> z) & 1u) acc = T(0);
+      buf_store(acc, y, point_off<T>(out, i, j, k, N));
+    }
+    // slide to plane k+1
+#pragma unroll
+    for (int r = 0; r < KJ + 1; ++r) B[r] = A[r + 1];
+#pragma unroll
+    for (int r = 0; r < KJ + 1; ++r) A[r] = C[r];
+    A[KJ + 1] = nA;
+#pragma unroll
+    for (int r = 0; r < KJ + 1; ++r) C[r] = nC[r];
+  }
+}
+
 // Fused reverse mode of the macro-local P1 div(k grad) apply:
 //   gx_p = (L(k) gy)_p,  gk_p = sum_{T containing p} 1/4 (D gy)_T . Gp_T (D x)_T
 template <typename T>
@@ -418,7 +495,7 @@ template <typename T>
 hipError_t launch_p1_apply(const P1Args<T> &a, int kind, const int4 *units, int nunits, hipStream_t s) {
   const dim3 grid(((nunits + 3) / 4) * a.lat.nt);
   if (kind == P1_LAPLACE)
-    hipLaunchKernelGGL((k_p1_apply<T, P1_LAPLACE>), grid, dim3(256), 0, s, a, units, nunits);
+    hipLaunchKernelGGL((k_p1_stencil<T>), grid, dim3(256), 0, s, a, units, nunits);
   else
     hipLaunchKernelGGL((k_p1_apply<T, P1_DIVKGRAD>), grid, dim3(256), 0, s, a, units, nunits);
   return hipGetLastError();
