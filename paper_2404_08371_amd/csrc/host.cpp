@@ -482,13 +482,13 @@ tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const
     const int N = S.N;
     if (kind == P1_LAPLACE) {
       // stencil tiles (2.5-D blocking): rows j0 .. j0+3, points i0 .. i0+61,
-      // planes k0 .. k0+7 (the planes where the tile has points).  i0 varies
+      // planes k0 .. k0+3 (the planes where the tile has points).  i0 varies
       // fastest: concurrent wavefronts cover whole rows of the same planes,
       // so memory is read in long contiguous runs.
-      for (int k0 = 0; k0 <= N; k0 += 8)
+      for (int k0 = 0; k0 <= N; k0 += 4)
         for (int j0 = 0; j0 <= N - k0; j0 += 4)
           for (int i0 = 0; i0 <= N - j0 - k0; i0 += 62)
-            ch.push_back(make_int4(j0, i0, k0, std::min(k0 + 8, N - i0 - j0 + 1)));
+            ch.push_back(make_int4(j0, i0, k0, std::min(k0 + 4, N - i0 - j0 + 1)));
     } else {
       // row march: plane k, 62 points i0.., rows j0 .. j1-1 (8 rows; the rows
       // of the plane with points at i >= i0)

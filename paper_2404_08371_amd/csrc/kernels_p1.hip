@@ -212,11 +212,14 @@ __device__ __forceinline__ float buf_load(float, Rsrc r, int off) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 typedef unsigned int U32x2 __attribute__((ext_vector_type(2)));
+// outputs are written once and not read again by the kernel: non-temporal
+// stores (cache policy bit NT) keep them from evicting input rows from L2
+constexpr int kStoreNT = 2;
 __device__ __forceinline__ void buf_store(double v, Rsrc r, int off) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, v), r, off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, v), r, off, 0, kStoreNT);
 }
 __device__ __forceinline__ void buf_store(float v, Rsrc r, int off) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, kStoreNT);
 }
 // byte offset of point (i, j, k) of the block, or kFar if `ok` is false
 template <typename T>
@@ -365,7 +368,8 @@ __global__ __launch_bounds__(256) void k_p1_apply(P1Args<T> a, const int4 *__res
 
 // Constant-coefficient stencil, 2.5-D blocking: a wavefront owns a tile of
 // KJ rows x 62 points (rows j0 .. j0+KJ-1, points i0 .. i0+61) and marches
-// through planes k0 .. k1-1.  It holds plane k's rows j0-1 .. j0+KJ, plane
+// through planes k0 .. k1-1 (4 planes: short marches keep many wavefronts,
+// and so many loads, in flight).  It holds plane k's rows j0-1 .. j0+KJ, plane
 // k-1's rows j0 .. j0+KJ and plane k+1's rows j0-1 .. j0+KJ-1; a step to
 // plane k+1 loads KJ + 2 rows (plane k+2's KJ + 1, plane k+1's row j0+KJ)
 // for KJ output rows, issued one step ahead.
