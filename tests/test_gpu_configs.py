@@ -1,6 +1,8 @@
 """GPU parity at the full sizes of the benchmark workloads.
 
-* P1 Laplacian, reference tet, level 4 (969 DoFs): every entry vs the oracle.
+* P1 Laplacian, reference tet, level 4 (969 DoFs): every entry vs the oracle;
+  and at level 7 (both boundary conditions) and on the 6-macro cube at level 6,
+  where the stencil kernel's tiles repeat in every direction.
 * P2 -div(k grad), unit cube as 6 macro-tets, level 6 (2,146,689 DoFs), in the
   launch configuration the benchmark times (autotuned tile shape): every entry
   vs the oracle, FP64 relative 1e-12.
@@ -41,6 +43,23 @@ def test_p1_laplace_reference_tet_level4_full():
     e2, ei = rel(y, pr.apply(W.uniform_from_keys(1, pr.keys)))
     assert e2 <= 1e-12 and ei <= 1e-12
     assert pr.n_unique == 969 and (~pr.boundary).sum() == 455
+
+
+@pytest.mark.parametrize("mesh,level,bc", [("ref", 7, O.BC_DIRICHLET_ZERO), ("ref", 7, O.BC_NONE),
+                                           ("cube", 6, O.BC_DIRICHLET_ZERO)])
+def test_p1_laplace_multi_tile_full(mesh, level, bc):
+    """Every entry vs the oracle at sizes where the stencil kernel's tiles
+    (62 points x 4 rows x 4 planes) repeat in every direction with ragged ends."""
+    print("P1 multi-tile case", mesh, level, bc, flush=True)
+    v, t = {"ref": W.meshes.ref_tet, "cube": W.meshes.kuhn_cube}[mesh]()
+    m = T.Mesh(v, t, level)
+    op = T.Operator(m, T.P1_LAPLACE, T.F64, bc)
+    info = m.dof_info(1, owner=False, boundary=False)
+    y = op.apply(torch.tensor(W.uniform_from_keys(1, info["keys"]), device="cuda")).cpu().numpy()
+    pr = O.Problem(v, t, level, O.P1_LAPLACE, bc)
+    e2, ei = rel(y, pr.apply(W.uniform_from_keys(1, pr.keys)))
+    print("errors", e2, ei)
+    assert e2 <= 1e-12 and ei <= 1e-12
 
 
 def test_p2_divkgrad_cube_level6_full_in_bench_configuration():
