@@ -30,6 +30,11 @@ struct tmf_batch {
   int nchunks = 0;
   DevBuf<int> first;
   DevBuf<uint8_t> owner;  // only when some instance has several macros
+  // seam reduction of all instances in one launch, per tile shape
+  DevBuf<uint8_t> seaminst[kNumTileCfg];
+  DevBuf<int4> seamwork[kNumTileCfg];
+  int nseamwork[kNumTileCfg] = {0};
+  int seamrows[kNumTileCfg] = {0};  // tile-row table entries staged in LDS by the seam reduction
 };
 
 struct tmf_ir {
@@ -57,7 +62,10 @@ template <typename T>
 hipError_t batch_apply_t(tmf_batch *b, const void *coeff, const void *x, void *y, const uint8_t *active,
                          hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   T *yy = static_cast<T *>(y);
-  hipError_t e = launch_fill<T>(yy, b->off[b->count], T(0), s);
+  hipError_t e = hipSuccess;
+  // every entry of an active instance is written by the element kernel or the
+  // seam reduction; inactive instances are left at zero
+  if (active) e = launch_fill<T>(yy, b->off[b->count], T(0), s);
   if (e != hipSuccess) return e;
   TileArgs<T> a;
   a.inst = reinterpret_cast<const InstDesc<T> *>(b->desc.p);
@@ -73,19 +81,10 @@ hipError_t batch_apply_t(tmf_batch *b, const void *coeff, const void *x, void *y
   e = launch_tile_apply<T>(a, b->kind, TMF_MAP_AFFINE, b->tile_cfg, s);
   if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
   if (e != hipSuccess) return e;
-  for (int i = 0; i < b->count; ++i) {
-    const tmf_op *op = b->ops[i];
-    if (op->ngroups == 0) continue;
-    GroupArgs g;
-    g.ptr = op->gptr.p;
-    g.idx = op->gidx.p;
-    g.ngroups = op->ngroups;
-    g.n_local = op->n_local;
-    g.ncomp = op->ncomp;
-    e = launch_interface_sum<T>(g, yy + b->off[i], s);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  // seam and interface reduction of every instance, one launch
+  const int c = b->tile_cfg;
+  return launch_seam_gather<T>(reinterpret_cast<const SeamInst<T> *>(b->seaminst[c].p), b->seamwork[c].p,
+                               b->nseamwork[c], yy, active, 0, b->ncomp, c, b->seamrows[c], s);
 }
 
 tmf_status batch_apply(tmf_batch *b, const void *coeff, const void *x, void *y, const uint8_t *active,
@@ -160,8 +159,31 @@ tmf_status tmf_batch_create(tmf_op *const *ops, int count, tmf_batch **out) {
           for (int by = 0; by < n - bz; by += TY)
             for (int bx = 0; bx < n - bz - by; bx += TX) tl.push_back(make_int4(i, int(mac), pack_base(bx, by, bz), 0));
     }
+    // .w = tile id within the instance (the operator's own enumeration order)
+    {
+      std::vector<int> next(count, 0);
+      for (int4 &t4 : tl) t4.w = next[t4.x]++;
+    }
     b->ntiles[cfg] = static_cast<int>(tl.size());
     st = b->tiles[cfg].upload(tl.data(), tl.size());
+  }
+  for (int cfg = 0; cfg < kNumTileCfg && st == TMF_OK; ++cfg) {
+    std::vector<int4> w;
+    for (int i = 0; i < count; ++i) group_work(ops[i], i, w);
+    for (int i = 0; i < count; ++i) seam_work(ops[i], cfg, i, w);
+    b->nseamwork[cfg] = static_cast<int>(w.size());
+    for (int i = 0; i < count; ++i) b->seamrows[cfg] = std::max(b->seamrows[cfg], seam_rows_lds(ops[i]->seamrows[cfg]));
+    st = b->seamwork[cfg].upload(w.data(), w.size());
+    if (st != TMF_OK) break;
+    if (b->prec == TMF_F64) {
+      std::vector<SeamInst<double>> si;
+      for (int i = 0; i < count; ++i) si.push_back(seam_inst<double>(ops[i], cfg, b->off[i]));
+      st = b->seaminst[cfg].upload(reinterpret_cast<uint8_t *>(si.data()), si.size() * sizeof(si[0]));
+    } else {
+      std::vector<SeamInst<float>> si;
+      for (int i = 0; i < count; ++i) si.push_back(seam_inst<float>(ops[i], cfg, b->off[i]));
+      st = b->seaminst[cfg].upload(reinterpret_cast<uint8_t *>(si.data()), si.size() * sizeof(si[0]));
+    }
   }
   // reduction chunks
   std::vector<ChunkDesc> ch;

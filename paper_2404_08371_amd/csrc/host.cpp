@@ -502,16 +502,96 @@ tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const
     st = op->chunks.upload(ch.data(), ch.size());
   }
   if (st == TMF_OK && space == 2) {
-    const int n = mesh->n;
+    const int n = mesh->n, N = S.N;
+    size_t partial_bytes = 0;
     for (int cfg = 0; cfg < kNumTileCfg && st == TMF_OK; ++cfg) {
       const int TX = kTileCfg[cfg][0], TY = kTileCfg[cfg][1], TZ = kTileCfg[cfg][2];
+      // tiles, macro-major; .w = tile id within the operator
       std::vector<int4> tl;
       for (int64_t mac = 0; mac < mesh->nt; ++mac)
         for (int bz = 0; bz < n; bz += TZ)
           for (int by = 0; by < n - bz; by += TY)
-            for (int bx = 0; bx < n - bz - by; bx += TX) tl.push_back(make_int4(0, int(mac), pack_base(bx, by, bz), 0));
+            for (int bx = 0; bx < n - bz - by; bx += TX)
+              tl.push_back(make_int4(0, int(mac), pack_base(bx, by, bz), static_cast<int>(tl.size())));
       op->ntiles[cfg] = static_cast<int>(tl.size());
       st = op->tiles[cfg].upload(tl.data(), tl.size());
+      // first tile id of each box row (bz, by) within a macro
+      const int nbz = (n + TZ - 1) / TZ, nby = (n + TY - 1) / TY;
+      std::vector<int> rs(static_cast<size_t>(nbz) * nby, -1);
+      int id = 0;
+      for (int bz = 0; bz < n; bz += TZ)
+        for (int by = 0; by < n - bz; by += TY) {
+          rs[static_cast<size_t>(bz / TZ) * nby + by / TY] = id;
+          for (int bx = 0; bx < n - bz - by; bx += TX) ++id;
+        }
+      op->tpm[cfg] = id;
+      op->nby[cfg] = nby;
+      op->seamrows[cfg] = nbz * nby;
+      if (st == TMF_OK) st = op->rowstart[cfg].upload(rs.data(), rs.size());
+      // seam points: a lattice coordinate that is a positive multiple of the
+      // box extent (2 T points) lies on a face shared by two boxes
+      std::vector<int> pts;
+      for (int qz = 0; qz <= N; ++qz)
+        for (int qy = 0; qy <= N - qz; ++qy)
+          for (int qx = 0; qx <= N - qz - qy; ++qx)
+            if ((qx > 0 && qx % (2 * TX) == 0) || (qy > 0 && qy % (2 * TY) == 0) || (qz > 0 && qz % (2 * TZ) == 0))
+              pts.push_back(qx | (qy << 10) | (qz << 20));
+      op->nseam[cfg] = static_cast<int>(pts.size());
+      if (st == TMF_OK) st = op->seam[cfg].upload(pts.data(), pts.size());
+      const size_t R = static_cast<size_t>(2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1);
+      partial_bytes = std::max(partial_bytes, tl.size() * R * op->ncomp * (prec == TMF_F64 ? 8 : 4));
+    }
+    if (st == TMF_OK) st = op->partial.alloc(partial_bytes);
+    // interface-group members as (macro, lattice point), and per macro the
+    // zero patterns whose points have copies in other macros
+    {
+      std::vector<int> pk(static_cast<size_t>(S.L));
+      size_t l = 0;
+      for (int qz = 0; qz <= N; ++qz)
+        for (int qy = 0; qy <= N - qz; ++qy)
+          for (int qx = 0; qx <= N - qz - qy; ++qx) pk[l++] = qx | (qy << 10) | (qz << 20);
+      std::vector<int64_t> gpos(S.gidx.size());
+      std::vector<int> gpl(S.gidx.size());
+      std::vector<uint32_t> shm(static_cast<size_t>(mesh->nt), 0u);
+      if (S.gidx.size() > 0x7fffffff) st = fail(TMF_EINVAL, "too many interface copies for the seam reduction");
+      for (size_t g = 0; g + 1 < S.gptr.size() && st == TMF_OK; ++g) {
+        const int64_t len = S.gptr[g + 1] - S.gptr[g];
+        if (len > 256) {
+          st = fail(TMF_EINVAL, "an interface group has %lld copies (at most 256 supported)", (long long)len);
+          break;
+        }
+        for (int64_t q = S.gptr[g]; q < S.gptr[g + 1]; ++q) {
+          const int64_t slot = S.gidx[q], mac = slot / S.L;
+          const int p = pk[static_cast<size_t>(slot - mac * S.L)];
+          gpos[q] = (mac << 32) | static_cast<int64_t>(p);
+          gpl[q] = static_cast<int>(((q - S.gptr[g]) << 16) | len);
+          shm[mac] |= 1u << zero_pattern(p & 1023, (p >> 10) & 1023, p >> 20, N);
+        }
+      }
+      if (st == TMF_OK) st = op->gpos.upload(gpos.data(), gpos.size());
+      if (st == TMF_OK) st = op->gpl.upload(gpl.data(), gpl.size());
+      if (st == TMF_OK) st = op->shared.upload(shm.data(), shm.size());
+    }
+    op->ngroups = static_cast<int64_t>(S.gptr.size()) - 1;
+    if (st == TMF_OK) st = op->gptr.upload(S.gptr.data(), S.gptr.size());
+    if (st == TMF_OK) st = op->gidx.upload(S.gidx.data(), S.gidx.size());
+    for (int cfg = 0; cfg < kNumTileCfg && st == TMF_OK; ++cfg) {
+      if (prec == TMF_F64) {
+        SeamInst<double> si = seam_inst<double>(op, cfg, 0);
+        st = op->seaminst[cfg].upload(reinterpret_cast<uint8_t *>(&si), sizeof(si));
+      } else {
+        SeamInst<float> si = seam_inst<float>(op, cfg, 0);
+        st = op->seaminst[cfg].upload(reinterpret_cast<uint8_t *>(&si), sizeof(si));
+      }
+      // interface groups first: their chains of dependent loads then overlap
+      // the bulk of the seam points instead of forming the launch's tail
+      std::vector<int4> w;
+      group_work(op, 0, w);
+      op->ngroupwork[cfg] = static_cast<int>(w.size());
+      seam_work(op, cfg, 0, w);
+      op->nseamwork[cfg] = static_cast<int>(w.size());
+      op->nseamonly[cfg] = op->nseamwork[cfg] - op->ngroupwork[cfg];
+      if (st == TMF_OK) st = op->seamwork[cfg].upload(w.data(), w.size());
     }
   }
   if (st == TMF_OK) {
@@ -524,9 +604,11 @@ tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const
     }
   }
   if (st == TMF_OK) {
-    op->ngroups = static_cast<int64_t>(S.gptr.size()) - 1;
-    st = op->gptr.upload(S.gptr.data(), S.gptr.size());
-    if (st == TMF_OK) st = op->gidx.upload(S.gidx.data(), S.gidx.size());
+    if (space == 1) {
+      op->ngroups = static_cast<int64_t>(S.gptr.size()) - 1;
+      st = op->gptr.upload(S.gptr.data(), S.gptr.size());
+      if (st == TMF_OK) st = op->gidx.upload(S.gidx.data(), S.gidx.size());
+    }
     if (st == TMF_OK) st = op->owner.upload(S.owner.data(), S.owner.size());
   }
   if (st != TMF_OK) {
@@ -591,8 +673,6 @@ hipError_t apply_t(tmf_op *op, const void *coeff, const void *x, void *y, hipStr
     e = launch_p1_apply<T>(a, op->kind, op->chunks.p, op->nchunks, s);
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
   } else {
-    e = launch_fill<T>(yy, op->ncomp * op->n_local, T(0), s);
-    if (e != hipSuccess) return e;
     TileArgs<T> a;
     a.inst = reinterpret_cast<const InstDesc<T> *>(op->desc.p);
     a.tiles = op->tiles[op->tile_cfg].p;
@@ -606,6 +686,14 @@ hipError_t apply_t(tmf_op *op, const void *coeff, const void *x, void *y, hipStr
     if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
     e = launch_tile_apply<T>(a, op->kind, op->mesh->map, op->tile_cfg, s);
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
+    // seam reduction, with the interface sums unless a macro-local result is asked for
+    const int c = op->tile_cfg;
+    if (e == hipSuccess)
+      e = launch_seam_gather<T>(reinterpret_cast<const SeamInst<T> *>(op->seaminst[c].p),
+                                op->seamwork[c].p + (interface ? 0 : op->ngroupwork[c]),
+                                interface ? op->nseamwork[c] : op->nseamonly[c], yy, nullptr, interface ? 0 : 1,
+                                op->ncomp, c, seam_rows_lds(op->seamrows[c]), s);
+    return e;
   }
   if (e != hipSuccess || !interface) return e;
   return launch_interface_sum<T>(group_args(op), yy, s);

@@ -85,7 +85,64 @@ struct tmf_op {
   DevBuf<uint8_t> desc;  // one InstDesc of the op's precision
   DevBuf<int4> chunks;   // P1: row-march work units (k, i0, j0, j1) of one macro lattice
   int nchunks = 0;
+  // P2 tiles: seam points of one macro lattice and tile-row starts, per tile
+  // shape; partial sums of the seam points (operator scratch)
+  DevBuf<int> seam[kNumTileCfg], rowstart[kNumTileCfg];
+  int nseam[kNumTileCfg] = {0}, nby[kNumTileCfg] = {0}, tpm[kNumTileCfg] = {0};
+  DevBuf<uint8_t> partial;
+  DevBuf<uint8_t> seaminst[kNumTileCfg];  // one SeamInst of the op's precision
+  DevBuf<int4> seamwork[kNumTileCfg];     // interface-group entries, then seam entries
+  int nseamwork[kNumTileCfg] = {0}, nseamonly[kNumTileCfg] = {0}, ngroupwork[kNumTileCfg] = {0};
+  DevBuf<uint32_t> shared;                // per macro: zero patterns with copies in other macros
+  DevBuf<int64_t> gpos;                   // per interface-group member: macro << 32 | packed lattice point
+  DevBuf<int> gpl;                        // per interface-group member: position << 16 | group size
+  int seamrows[kNumTileCfg] = {0};        // tile-row table entries per macro, per tile shape
 };
+
+// seam-reduction descriptor of an op with tile shape `cfg` at offset `yoff`
+template <typename T>
+inline SeamInst<T> seam_inst(const tmf_op *op, int cfg, int64_t yoff) {
+  SeamInst<T> a;
+  a.pts = op->seam[cfg].p;
+  a.npts = op->nseam[cfg];
+  a.rowstart = op->rowstart[cfg].p;
+  a.nby = op->nby[cfg];
+  a.tpm = op->tpm[cfg];
+  a.n = op->mesh->n;
+  a.N = op->N;
+  a.L = static_cast<int>(op->L);
+  a.dirichlet = op->bc == TMF_BC_DIRICHLET_ZERO;
+  a.n_local = op->n_local;
+  a.yoff = yoff;
+  a.bnd = op->bnd.p;
+  a.partial = reinterpret_cast<const T *>(op->partial.p);
+  a.shared = op->shared.p;
+  a.gidx = op->gidx.p;
+  a.gpos = op->gpos.p;
+  a.gpl = op->gpl.p;
+  return a;
+}
+
+// seam work entries (instance, macro, first point, 0) of an op
+inline void seam_work(const tmf_op *op, int cfg, int inst, std::vector<int4> &w) {
+  for (int64_t m = 0; m < op->mesh->nt; ++m)
+    for (int p0 = 0; p0 < op->nseam[cfg]; p0 += 256) w.push_back(make_int4(inst, static_cast<int>(m), p0, 0));
+}
+// interface work entries (instance, first member, end member, 1) of an op:
+// whole groups, at most 256 members per entry
+inline void group_work(const tmf_op *op, int inst, std::vector<int4> &w) {
+  const std::vector<int64_t> &gp = op->mesh->sp[op->space].gptr;
+  int64_t q0 = 0;
+  for (size_t g = 0; g + 1 < gp.size(); ++g) {
+    if (gp[g + 1] - q0 > 256) {
+      w.push_back(make_int4(inst, static_cast<int>(q0), static_cast<int>(gp[g]), 1));
+      q0 = gp[g];
+    }
+  }
+  if (gp.size() > 1 && gp.back() > q0) w.push_back(make_int4(inst, static_cast<int>(q0), static_cast<int>(gp.back()), 1));
+}
+// tile-row table entries staged in LDS by the seam reduction (0: read from global memory)
+inline int seam_rows_lds(int nrows) { return nrows <= kSeamRowsLds ? nrows : 0; }
 
 // device descriptor of an op, for the element kernels
 template <typename T>
@@ -98,6 +155,7 @@ InstDesc<T> make_desc(const tmf_op *op, int64_t off) {
   d.off = off;
   d.n_local = op->n_local;
   d.bnd = op->bnd.p;
+  d.partial = reinterpret_cast<T *>(op->partial.p);
   d.geo = reinterpret_cast<const TypeGeo<T> *>(op->geo.p);
   d.mgeo = reinterpret_cast<const MacroGeo<T> *>(op->mgeo.p);
   return d;

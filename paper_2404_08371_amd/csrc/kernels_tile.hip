@@ -8,9 +8,14 @@
 //   2. applies the fused local operator to every micro-tet of the box -- one
 //      lane per micro-tet, one type per wavefront -- and accumulates the 10
 //      (or 30) local results into an FP64 LDS copy of y,
-//   3. writes y: points touched only by this box are stored directly; points
-//      on the box faces shared with neighbouring boxes are added into y
-//      (zero-filled beforehand) with hardware FP atomics.
+//   3. writes y at the points that belong to this box alone, and its partial
+//      sums at the points of box faces shared with neighbouring boxes to the
+//      instance's partial buffer; a second kernel (k_seam) adds the partials
+//      of each shared point in a fixed order.  Every entry of y is written
+//      once: no global atomics and no zero fill of y.  Inside a box the six
+//      wavefronts add into the LDS copy of y with LDS atomics, whose order
+//      across wavefronts is not fixed, so two applies can differ in the last
+//      bits of a sum (both within rounding of the exact one).
 // The local operator is never formed (remark on fused local quadrature after
 // algorithm "LocalApply"): for affine elements the gradient of a P2 field is
 // a P1 field, grad u = sum_a lambda_a g_a, and every integral becomes a
@@ -542,24 +547,154 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
   }
   __syncthreads();
 
-  // 3. write back: points touched only by this box are stored, shared face points added
+  // 3. write back: points of this box alone go to y (Dirichlet DoFs as 0),
+  // points of shared box faces to this tile's partials [component][box point]
+  T *pt = D->partial + static_cast<int64_t>(tl.w) * NC * R;
   for (int r = tid; r < R; r += NTH) {
     const int row = r / RX, rx = r - row * RX;
     const int info = sri[row], lim = info >> 8, qi = 2 * bx0 + rx;
     if (qi > lim) continue;
     const int zp = (qi == lim) | ((qi == 0) << 1) | (info & 12);
-    if ((bnd >> zp) & 1u) continue;
     const bool excl = ((info >> 4) & 1) && ((rx & 1) || ((rx > 0 || bx0 == 0) && rx < 2 * TX));
-    const int off = srb[row] + qi;
     const int sl = lds_slot(rx, row, OO, RXP);
+    if (excl) {
+      const bool dir = (bnd >> zp) & 1u;
+      const int off = srb[row] + qi;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      if (excl)
-        yb[c][off] = T(sy[c][sl]);
-      else
-        atomicAdd(yb[c] + off, T(sy[c][sl]));
+      for (int c = 0; c < NC; ++c) __builtin_nontemporal_store(dir ? T(0) : T(sy[c][sl]), &yb[c][off]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) __builtin_nontemporal_store(T(sy[c][sl]), &pt[c * R + r]);
     }
   }
+}
+
+// Seam reduction.  A lattice point q lies on a face shared by two boxes in
+// dimension d when q_d is a positive multiple of 2 T_d; then the boxes at
+// q_d / 2 - T_d (q on its upper face) and q_d / 2 (lower face) both hold a
+// partial for it, otherwise the one box at T_d floor(q_d / (2 T_d)).  Of the
+// up to 8 candidate boxes those that exist (bx + by + bz <= n - 1) each wrote
+// their partial; they are added in a fixed order (z, y, x; lower first).
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ bool is_seam(int qx, int qy, int qz) {
+  return (qx > 0 && qx % (2 * TX) == 0) || (qy > 0 && qy % (2 * TY) == 0) || (qz > 0 && qz % (2 * TZ) == 0);
+}
+
+template <typename T, int NC, int TX, int TY, int TZ>
+__device__ __forceinline__ void seam_sum(const SeamInst<T> &a, const int *rs, int m, int qx, int qy, int qz,
+                                         T acc[NC]) {
+  constexpr int RX = 2 * TX + 1, RY = 2 * TY + 1, R = RX * RY * (2 * TZ + 1);
+  auto lower = [](int q, int t) { return (q > 0 && q % (2 * t) == 0) ? q / 2 - t : t * (q / (2 * t)); };
+  const int x0 = lower(qx, TX), y0 = lower(qy, TY), z0 = lower(qz, TZ);
+  const int nx = (qx > 0 && qx % (2 * TX) == 0) ? 2 : 1;
+  const int ny = (qy > 0 && qy % (2 * TY) == 0) ? 2 : 1;
+  const int nz = (qz > 0 && qz % (2 * TZ) == 0) ? 2 : 1;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = T(0);
+  for (int iz = 0; iz < nz; ++iz)
+    for (int iy = 0; iy < ny; ++iy)
+      for (int ix = 0; ix < nx; ++ix) {
+        const int bx = x0 + ix * TX, by = y0 + iy * TY, bz = z0 + iz * TZ;
+        if (bx + by + bz > a.n - 1) continue;
+        const int64_t tile = static_cast<int64_t>(m) * a.tpm + rs[(bz / TZ) * a.nby + by / TY] + bx / TX;
+        const int r = (qx - 2 * bx) + RX * ((qy - 2 * by) + RY * (qz - 2 * bz));
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] += a.partial[(tile * NC + c) * R + r];
+      }
+}
+
+// Work entries: (instance, macro, first seam point, 0) reduce up to 256 seam
+// points of one macro; (instance, first member, end member, 1) reduce whole
+// interface groups, one thread per member (at most 256 members).  The tile-row
+// starts of the instance are staged in dynamic LDS (`rows_lds` entries; a
+// larger table is read from global memory).
+template <typename T, int NC, int TX, int TY, int TZ>
+__global__ __launch_bounds__(256) void k_seam(const SeamInst<T> *__restrict__ insts, const int4 *__restrict__ work,
+                                              T *__restrict__ y, const uint8_t *__restrict__ active, int local,
+                                              int rows_lds) {
+  extern __shared__ int srs[];
+  __shared__ T sv[NC][256];
+  __shared__ uint8_t sd[256];
+  const int4 w = work[blockIdx.x];
+  if (active != nullptr && active[w.x] == 0) return;
+  const SeamInst<T> &a = insts[w.x];
+  const int t = threadIdx.x;
+  const bool grp = w.w == 1;
+  // this thread's first loads, issued before the row-table staging
+  bool mine;
+  int pk = 0, pl = 0, m = 0;  // threads past the entry's end keep point 0 of macro 0
+  int64_t slot = 0;
+  if (!grp) {
+    m = w.y;
+    const int p = w.z + t;
+    mine = p < a.npts;
+    if (mine) pk = a.pts[p];
+  } else {
+    const int q = w.y + t;
+    mine = q < w.z;
+    if (mine) {
+      const int64_t pos = a.gpos[q];
+      slot = a.gidx[q];
+      pl = a.gpl[q];
+      m = static_cast<int>(pos >> 32);
+      pk = static_cast<int>(pos & 0xffffffff);
+    }
+  }
+  const int nrows = ((a.n + TZ - 1) / TZ) * a.nby;
+  const bool in_lds = nrows <= rows_lds;
+  if (in_lds)
+    for (int e = t; e < nrows; e += 256) srs[e] = a.rowstart[e];
+  __syncthreads();
+  const int *rs = in_lds ? srs : a.rowstart;
+  T *yi = y + a.yoff;
+  const int qx = pk & 1023, qy = (pk >> 10) & 1023, qz = pk >> 20;
+  const int z = zero_pattern(qx, qy, qz, a.N);
+  const bool dir = a.dirichlet && ((a.bnd[m] >> z) & 1u);
+  if (!grp) {
+    // seam points of macro m; points with copies in other macros are left to
+    // their interface group (unless a macro-local result is asked for)
+    if (!mine || (!local && ((a.shared[m] >> z) & 1u))) return;
+    slot = static_cast<int64_t>(m) * a.L + row_base(qy, qz, a.N) + qx;
+    T acc[NC];
+    if (dir) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] = T(0);
+    } else {
+      seam_sum<T, NC, TX, TY, TZ>(a, rs, m, qx, qy, qz, acc);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) __builtin_nontemporal_store(acc[c], &yi[slot + c * a.n_local]);
+    return;
+  }
+  // interface groups: each member's macro-local value (seam sum or the tile
+  // kernel's store) goes to LDS; every member then adds its group's values in
+  // ascending member order, so all copies receive the same sum
+  if (mine) {
+    T v[NC];
+    if (is_seam<TX, TY, TZ>(qx, qy, qz)) {
+      seam_sum<T, NC, TX, TY, TZ>(a, rs, m, qx, qy, qz, v);
+    } else {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[c] = yi[slot + c * a.n_local];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) sv[c][t] = v[c];
+    sd[t] = dir;
+  }
+  __syncthreads();
+  if (!mine) return;
+  const int len = pl & 0xffff, h = t - (pl >> 16);
+  T sum[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) sum[c] = T(0);
+  bool gdir = false;
+  for (int i = h; i < h + len; ++i) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) sum[c] += sv[c][i];
+    gdir = gdir || sd[i];
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) __builtin_nontemporal_store(gdir ? T(0) : sum[c], &yi[slot + c * a.n_local]);
 }
 
 template <typename T, int KIND, int MAP, int TX, int TY, int TZ>
@@ -599,5 +734,31 @@ hipError_t launch_tile_apply(const TileArgs<T> &a, int kind, int map, int cfg, h
 
 template hipError_t launch_tile_apply<double>(const TileArgs<double> &, int, int, int, hipStream_t);
 template hipError_t launch_tile_apply<float>(const TileArgs<float> &, int, int, int, hipStream_t);
+
+template <typename T>
+hipError_t launch_seam_gather(const SeamInst<T> *inst, const int4 *work, int nwork, T *y, const uint8_t *active,
+                              int local, int ncomp, int cfg, int rows_lds, hipStream_t s) {
+  if (nwork == 0) return hipSuccess;
+  const dim3 grid(nwork);
+  const size_t sh = static_cast<size_t>(rows_lds) * sizeof(int);
+  if (ncomp == 3) {
+    if (cfg != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_seam<T, 3, 4, 4, 4>), grid, dim3(256), sh, s, inst, work, y, active, local, rows_lds);
+    return hipGetLastError();
+  }
+  switch (cfg) {
+    case 0: hipLaunchKernelGGL((k_seam<T, 1, 4, 4, 4>), grid, dim3(256), sh, s, inst, work, y, active, local, rows_lds); break;
+    case 1: hipLaunchKernelGGL((k_seam<T, 1, 8, 4, 2>), grid, dim3(256), sh, s, inst, work, y, active, local, rows_lds); break;
+    case 2: hipLaunchKernelGGL((k_seam<T, 1, 8, 4, 4>), grid, dim3(256), sh, s, inst, work, y, active, local, rows_lds); break;
+    case 3: hipLaunchKernelGGL((k_seam<T, 1, 4, 4, 8>), grid, dim3(256), sh, s, inst, work, y, active, local, rows_lds); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_seam_gather<double>(const SeamInst<double> *, const int4 *, int, double *,
+                                               const uint8_t *, int, int, int, int, hipStream_t);
+template hipError_t launch_seam_gather<float>(const SeamInst<float> *, const int4 *, int, float *, const uint8_t *,
+                                              int, int, int, int, hipStream_t);
 
 }  // namespace tmf

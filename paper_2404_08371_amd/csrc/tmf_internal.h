@@ -122,9 +122,10 @@ struct InstDesc {
   const uint32_t *bnd;          // per macro boundary table
   const TypeGeo<T> *geo;        // per macro x 6 types
   const MacroGeo<T> *mgeo;      // per macro (curved maps)
+  T *partial;                   // tile partial sums of seam points: [tile][component][box point]
 };
 
-// tile = (instance, macro, bx0 | by0 << 10 | bz0 << 20, 0) in micro-cube units
+// tile = (instance, macro, bx0 | by0 << 10 | bz0 << 20, tile id within the instance) in micro-cube units
 __host__ __device__ inline int pack_base(int bx, int by, int bz) { return bx | (by << 10) | (bz << 20); }
 
 template <typename T>
@@ -150,6 +151,36 @@ struct GroupArgs {
 
 constexpr int kQStride = 45;  // floats per quadrature point in qtab
 
+// Seam and interface reduction, one launch for a whole batch.  y at every
+// seam point (a lattice point on a face shared by tile boxes) = the
+// fixed-order sum of the partials of the tiles containing it; every copy of a
+// DoF shared by several macros = the sum, in ascending slot order, of its
+// copies' macro-local values (each from the partials if it is a seam point,
+// else the value the element kernel stored).  Work entries: (instance, macro,
+// first seam point, 0) per 256 seam points and (instance, first group, 0, 1)
+// per 256 interface groups.
+template <typename T>
+struct SeamInst {
+  const int *pts;       // seam points of one macro lattice: qx | qy << 10 | qz << 20
+  int npts;
+  const int *rowstart;  // first tile id of box row (bz / TZ, by / TY) within a macro
+  int nby;              // row stride of rowstart
+  int tpm;              // tiles per macro
+  int n, N, L, dirichlet;
+  int64_t n_local;      // component stride
+  int64_t yoff;         // offset of the instance in the concatenated vectors
+  const uint32_t *bnd;
+  const T *partial;
+  // copies of DoFs shared with other macros (interface groups, members ascending)
+  const uint32_t *shared;  // per macro: bit z set if points of zero pattern z have copies elsewhere
+  const int64_t *gidx;     // per member: macro-local slot
+  const int64_t *gpos;     // per member: macro << 32 | qx | qy << 10 | qz << 20
+  const int *gpl;          // per member: position in its group << 16 | group size
+};
+
+// largest tile-row table staged in LDS by the seam reduction (entries)
+constexpr int kSeamRowsLds = 8192;
+
 // launchers (kernels.hip); return the HIP error of the launch
 template <typename T>
 hipError_t launch_p1_apply(const P1Args<T> &a, int kind, const int4 *chunks, int nchunks, hipStream_t s);
@@ -157,6 +188,9 @@ template <typename T>
 hipError_t launch_p1_adjoint(const P1AdjArgs<T> &a, const int4 *chunks, int nchunks, hipStream_t s);
 template <typename T>
 hipError_t launch_tile_apply(const TileArgs<T> &a, int kind, int map, int tile_cfg, hipStream_t s);
+template <typename T>
+hipError_t launch_seam_gather(const SeamInst<T> *inst, const int4 *work, int nwork, T *y, const uint8_t *active,
+                              int local, int ncomp, int tile_cfg, int rows_lds, hipStream_t s);
 template <typename T>
 hipError_t launch_interface_sum(const GroupArgs &g, T *y, hipStream_t s);
 template <typename T>

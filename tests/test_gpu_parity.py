@@ -91,3 +91,49 @@ def test_every_tile_shape(cfg, kind, prec):
                  torch.tensor(k, dtype=dt, device="cuda") if k is not None else None)
     e2, ei = rel_err(y.double().cpu().numpy(), pr.apply(x, k))
     assert ei <= (1e-12 if prec == T.F64 else 2e-5), (e2, ei)
+
+
+@pytest.mark.parametrize("mesh,level,kind", [("cube", 3, O.P2_DIVKGRAD), ("cube", 4, O.P2_LAPLACE),
+                                             ("flatshell", 2, O.P2V_EPSILON), ("shell", 1, O.P2V_EPSILON)])
+@pytest.mark.parametrize("bc", [O.BC_DIRICHLET_ZERO, O.BC_NONE])
+def test_local_apply_then_interface_sum_is_the_apply(mesh, level, kind, bc):
+    """The macro-local apply (seam reduction only) followed by the interface sum
+    gives the full apply: the same values summed in the same order, up to the
+    order of the in-box LDS accumulation across wavefronts.  Outputs start as
+    NaN, so a slot that no kernel writes (or that is read before it is
+    written) shows."""
+    print("local case", mesh, level, kind, bc, flush=True)
+    m, op = lib_problem(mesh, level, kind, bc, T.F64)
+    info = m.dof_info(op.space, owner=False, boundary=False)
+    x, k = inputs(kind, info["keys"], info["xyz"], 4)
+    xt = torch.tensor(x, device="cuda")
+    kt = torch.tensor(k, device="cuda") if k is not None else None
+    y = op.apply(xt, kt, out=torch.full_like(xt, float("nan")))
+    yl = op.interface_sum_(op.apply_local(xt, kt, out=torch.full_like(xt, float("nan"))))
+    assert not torch.isnan(y).any() and not torch.isnan(yl).any()
+    scale = y.abs().max().item()
+    assert (y - yl).abs().max().item() <= 1e-14 * scale
+    pr = oracle_problem(mesh, level, kind, bc)
+    ref = pr.apply(*inputs(kind, pr.keys, pr.xyz, 4))
+    for v in (y, yl):
+        e2, ei = rel_err(v.cpu().numpy(), ref)
+        assert e2 <= 1e-12 and ei <= 1e-12, (e2, ei)
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+def test_repeated_applies_agree(cfg):
+    """Every entry of y is written by exactly one thread (outputs start as NaN);
+    repeated applies agree to rounding of the in-box LDS accumulation."""
+    print("repeat case", cfg, flush=True)
+    m, op = lib_problem("cube", 5, O.P2_DIVKGRAD, O.BC_DIRICHLET_ZERO, T.F64)
+    T.check(T.lib().tmf_op_set_tile(op.handle, cfg))
+    info = m.dof_info(2, owner=False, boundary=False)
+    x, k = inputs(O.P2_DIVKGRAD, info["keys"], info["xyz"], 5)
+    xt, kt = torch.tensor(x, device="cuda"), torch.tensor(k, device="cuda")
+    y0 = op.apply(xt, kt, out=torch.full_like(xt, float("nan")))
+    assert not torch.isnan(y0).any()
+    scale = y0.abs().max().item()
+    for _ in range(5):
+        y = op.apply(xt, kt, out=torch.full_like(xt, float("nan")))
+        assert not torch.isnan(y).any()
+        assert (y - y0).abs().max().item() <= 1e-14 * scale
