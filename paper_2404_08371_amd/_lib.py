@@ -5,6 +5,7 @@ loading fails loudly when it is missing -- there is no fallback path.
 """
 import ctypes
 import os
+import sys
 
 _PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtetmf.so")
 _LIB = None
@@ -96,3 +97,14 @@ def check(status):
         msg = lib().tmf_last_error().decode(errors="replace")
         raise TetmfError(status, msg)
     return status
+
+
+def release(handle, destroy_name):
+    """Destroy a library handle; skipped while the interpreter shuts down
+    (the HIP runtime and this module's globals may already be gone)."""
+    try:
+        if handle is None or not handle.value or sys.is_finalizing() or _LIB is None:
+            return
+        getattr(_LIB, destroy_name)(handle)
+    except (AttributeError, TypeError, ImportError):
+        pass

@@ -4,7 +4,7 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import check, lib
+from ._lib import check, lib, release
 from .operators import DTYPE, _stream_handle
 
 
@@ -79,10 +79,8 @@ class Batch:
         return cfg.value, ms.value
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().tmf_batch_destroy(h)
-            self._h = None
+        release(getattr(self, "_h", None), "tmf_batch_destroy")
+        self._h = None
 
 
 class IRSolver:
@@ -111,7 +109,5 @@ class IRSolver:
                  "converged": bool(st.converged), "seconds": st.seconds}, rel)
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().tmf_ir_destroy(h)
-            self._h = None
+        release(getattr(self, "_h", None), "tmf_ir_destroy")
+        self._h = None

@@ -125,8 +125,9 @@ inline SeamInst<T> seam_inst(const tmf_op *op, int cfg, int64_t yoff) {
 
 // seam work entries (instance, macro, first point, 0) of an op
 inline void seam_work(const tmf_op *op, int cfg, int inst, std::vector<int4> &w) {
+  const int chunk = 256 * (op->ncomp == 1 ? kSeamPointsPerThread : 1);
   for (int64_t m = 0; m < op->mesh->nt; ++m)
-    for (int p0 = 0; p0 < op->nseam[cfg]; p0 += 256) w.push_back(make_int4(inst, static_cast<int>(m), p0, 0));
+    for (int p0 = 0; p0 < op->nseam[cfg]; p0 += chunk) w.push_back(make_int4(inst, static_cast<int>(m), p0, 0));
 }
 // interface work entries (instance, first member, end member, 1) of an op:
 // whole groups, at most 256 members per entry

@@ -5,9 +5,10 @@
 // cube, and of neighbouring cubes, reuse DoFs already staged on chip).  It
 //   1. stages the (2TX+1)(2TY+1)(2TZ+1) P2 lattice points of the box (x, the
 //      coefficient, Dirichlet mask applied to x) from HBM into LDS,
-//   2. applies the fused local operator to every micro-tet of the box -- one
-//      lane per micro-tet, one type per wavefront -- and accumulates the 10
-//      (or 30) local results into an FP64 LDS copy of y,
+//   2. applies the fused local operator to every micro-tet of the box -- a
+//      lane per cube, each wavefront running a fixed subset of the six
+//      micro-tet types -- and accumulates the 10 (or 30) local results into
+//      an FP64 LDS copy of y,
 //   3. writes y at the points that belong to this box alone, and its partial
 //      sums at the points of box faces shared with neighbouring boxes to the
 //      instance's partial buffer; a second kernel (k_seam) adds the partials
@@ -327,14 +328,19 @@ struct TileCfg {
   static constexpr int C = TX * TY * TZ;
   static constexpr int NC = KIND == P2V_EPSILON ? 3 : 1;
   static constexpr bool HASK = KIND != P2_LAPLACE;
-  // 6 wavefronts per workgroup, wavefront w applying micro-tet type w to every
-  // cube of the box: the type is a compile-time constant inside each
-  // wavefront's loop (LDS node offsets become instruction immediates, the
-  // type's geometry is loaded once into scalar registers)
+  // Scalar kinds: WPG wavefronts per workgroup, wavefront w applying the
+  // micro-tet types t = w (mod WPG) to every cube of the box, so the type is
+  // a compile-time constant inside each loop (LDS node offsets become
+  // instruction immediates, the type's geometry is loaded once into scalar
+  // registers).  64-cube boxes use 3 wavefronts (two types each): more
+  // workgroups then fit per CU (LDS, not wave slots, becomes the limit),
+  // which overlaps more staging round trips -- 12% faster than 6 on the FP64
+  // div(k grad) kernel; 128-cube boxes keep 6.
   // (the epsilon element needs 124-235 VGPRs: there 4-wavefront groups, two
   // per CU, beat one 6-wavefront group; wavefronts then take (type, cube)
   // slots with a wave-uniform type)
-  static constexpr int NTH = KIND == P2V_EPSILON ? 256 : 384;
+  static constexpr int WPG = C == 64 ? 3 : 6;
+  static constexpr int NTH = KIND == P2V_EPSILON ? 256 : 64 * WPG;
   static_assert(C % 64 == 0, "every lane of a wavefront needs a cube: 64 | cubes per tile");
 };
 
@@ -519,17 +525,16 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
   __syncthreads();
 
   // 2. micro-tets
-  if constexpr (NTH == 384) {
-    // wavefront w applies type w to every cube
+  if constexpr (KIND != P2V_EPSILON) {
+    // wavefront w applies the types t = w (mod WPG) to every cube
+    constexpr int WPG = Cfg::WPG;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-    switch (w) {
-      case 0: type_loop<T, KIND, MAP, TX, TY, TZ, 0, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
-      case 1: type_loop<T, KIND, MAP, TX, TY, TZ, 1, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
-      case 2: type_loop<T, KIND, MAP, TX, TY, TZ, 2, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
-      case 3: type_loop<T, KIND, MAP, TX, TY, TZ, 3, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
-      case 4: type_loop<T, KIND, MAP, TX, TY, TZ, 4, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
-      default: type_loop<T, KIND, MAP, TX, TY, TZ, 5, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane); break;
-    }
+    if (0 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 0, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane);
+    if (1 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 1, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane);
+    if (2 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 2, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane);
+    if (3 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 3, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane);
+    if (4 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 4, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane);
+    if (5 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 5, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane);
   } else {
     // slot e -> (type e / C, cube e % C); 64 | C makes the type wave-uniform
     constexpr int C = Cfg::C;
@@ -564,7 +569,9 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
       for (int c = 0; c < NC; ++c) __builtin_nontemporal_store(dir ? T(0) : T(sy[c][sl]), &yb[c][off]);
     } else {
 #pragma unroll
-      for (int c = 0; c < NC; ++c) __builtin_nontemporal_store(T(sy[c][sl]), &pt[c * R + r]);
+      // plain stores: the gather kernel reads these next (measured faster
+      // than non-temporal ones, and than a compact surface-only layout)
+      for (int c = 0; c < NC; ++c) pt[c * R + r] = T(sy[c][sl]);
     }
   }
 }
@@ -589,22 +596,44 @@ __device__ __forceinline__ void seam_sum(const SeamInst<T> &a, const int *rs, in
   const int nx = (qx > 0 && qx % (2 * TX) == 0) ? 2 : 1;
   const int ny = (qy > 0 && qy % (2 * TY) == 0) ? 2 : 1;
   const int nz = (qz > 0 && qz % (2 * TZ) == 0) ? 2 : 1;
+  // all 8 candidates without branches, so their loads are in flight together:
+  // a candidate that does not exist reads entry 0 of the buffer and adds +0,
+  // which leaves the sum (started at +0) unchanged
+  T v[8][NC];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) acc[c] = T(0);
-  for (int iz = 0; iz < nz; ++iz)
-    for (int iy = 0; iy < ny; ++iy)
-      for (int ix = 0; ix < nx; ++ix) {
+  for (int iz = 0; iz < 2; ++iz)
+#pragma unroll
+    for (int iy = 0; iy < 2; ++iy)
+#pragma unroll
+      for (int ix = 0; ix < 2; ++ix) {
         const int bx = x0 + ix * TX, by = y0 + iy * TY, bz = z0 + iz * TZ;
-        if (bx + by + bz > a.n - 1) continue;
-        const int64_t tile = static_cast<int64_t>(m) * a.tpm + rs[(bz / TZ) * a.nby + by / TY] + bx / TX;
+        const bool ok = ix < nx && iy < ny && iz < nz && bx + by + bz <= a.n - 1;
+        const int e = 4 * iz + 2 * iy + ix;
+        const int64_t tile = static_cast<int64_t>(m) * a.tpm + rs[ok ? (bz / TZ) * a.nby + by / TY : 0] + bx / TX;
         const int r = (qx - 2 * bx) + RX * ((qy - 2 * by) + RY * (qz - 2 * bz));
 #pragma unroll
-        for (int c = 0; c < NC; ++c) acc[c] += a.partial[(tile * NC + c) * R + r];
+        for (int c = 0; c < NC; ++c) {
+          const T val = a.partial[ok ? (tile * NC + c) * R + r : 0];
+          v[e][c] = ok ? val : T(0);
+        }
       }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    T s = T(0);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s += v[e][c];
+    acc[c] = s;
+  }
 }
 
-// Work entries: (instance, macro, first seam point, 0) reduce up to 256 seam
-// points of one macro; (instance, first member, end member, 1) reduce whole
+// seam points per thread of a seam work entry (256 threads)
+template <int NC>
+struct SeamPPT {
+  static constexpr int value = NC == 1 ? kSeamPointsPerThread : 1;
+};
+
+// Work entries: (instance, macro, first seam point, 0) reduce up to 256 PPT
+// seam points of one macro; (instance, first member, end member, 1) reduce whole
 // interface groups, one thread per member (at most 256 members).  The tile-row
 // starts of the instance are staged in dynamic LDS (`rows_lds` entries; a
 // larger table is read from global memory).
@@ -612,6 +641,7 @@ template <typename T, int NC, int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) void k_seam(const SeamInst<T> *__restrict__ insts, const int4 *__restrict__ work,
                                               T *__restrict__ y, const uint8_t *__restrict__ active, int local,
                                               int rows_lds) {
+  constexpr int PPT = SeamPPT<NC>::value;
   extern __shared__ int srs[];
   __shared__ T sv[NC][256];
   __shared__ uint8_t sd[256];
@@ -621,23 +651,27 @@ __global__ __launch_bounds__(256) void k_seam(const SeamInst<T> *__restrict__ in
   const int t = threadIdx.x;
   const bool grp = w.w == 1;
   // this thread's first loads, issued before the row-table staging
-  bool mine;
-  int pk = 0, pl = 0, m = 0;  // threads past the entry's end keep point 0 of macro 0
+  int pks[PPT];
+  bool mine = false;
+  int pl = 0, m = 0;  // threads past the entry's end keep point 0 of macro 0
   int64_t slot = 0;
   if (!grp) {
     m = w.y;
-    const int p = w.z + t;
-    mine = p < a.npts;
-    if (mine) pk = a.pts[p];
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+      const int p = w.z + t + 256 * u;
+      pks[u] = p < a.npts ? a.pts[p] : -1;
+    }
   } else {
     const int q = w.y + t;
     mine = q < w.z;
+    pks[0] = 0;
     if (mine) {
       const int64_t pos = a.gpos[q];
       slot = a.gidx[q];
       pl = a.gpl[q];
       m = static_cast<int>(pos >> 32);
-      pk = static_cast<int>(pos & 0xffffffff);
+      pks[0] = static_cast<int>(pos & 0xffffffff);
     }
   }
   const int nrows = ((a.n + TZ - 1) / TZ) * a.nby;
@@ -647,25 +681,38 @@ __global__ __launch_bounds__(256) void k_seam(const SeamInst<T> *__restrict__ in
   __syncthreads();
   const int *rs = in_lds ? srs : a.rowstart;
   T *yi = y + a.yoff;
+  if (!grp) {
+    // seam points of macro m (PPT per thread, 256 apart); points with copies
+    // in other macros are left to their interface group (unless a
+    // macro-local result is asked for)
+    // every point's loads first, then the stores (the compiler cannot move a
+    // load of one point above the store of another: y and the partials may alias)
+    const uint32_t bm = a.dirichlet ? a.bnd[m] : 0u, sh = local ? 0u : a.shared[m];
+    T acc[PPT][NC];
+    int64_t sl[PPT];
+    bool wr[PPT], dz[PPT];
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+      const int pk = pks[u] < 0 ? 0 : pks[u];
+      const int qx = pk & 1023, qy = (pk >> 10) & 1023, qz = pk >> 20;
+      const int z = zero_pattern(qx, qy, qz, a.N);
+      wr[u] = pks[u] >= 0 && !((sh >> z) & 1u);
+      dz[u] = (bm >> z) & 1u;
+      sl[u] = static_cast<int64_t>(m) * a.L + row_base(qy, qz, a.N) + qx;
+      seam_sum<T, NC, TX, TY, TZ>(a, rs, m, qx, qy, qz, acc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < PPT; ++u)
+      if (wr[u])
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          __builtin_nontemporal_store(dz[u] ? T(0) : acc[u][c], &yi[sl[u] + c * a.n_local]);
+    return;
+  }
+  const int pk = pks[0];
   const int qx = pk & 1023, qy = (pk >> 10) & 1023, qz = pk >> 20;
   const int z = zero_pattern(qx, qy, qz, a.N);
   const bool dir = a.dirichlet && ((a.bnd[m] >> z) & 1u);
-  if (!grp) {
-    // seam points of macro m; points with copies in other macros are left to
-    // their interface group (unless a macro-local result is asked for)
-    if (!mine || (!local && ((a.shared[m] >> z) & 1u))) return;
-    slot = static_cast<int64_t>(m) * a.L + row_base(qy, qz, a.N) + qx;
-    T acc[NC];
-    if (dir) {
-#pragma unroll
-      for (int c = 0; c < NC; ++c) acc[c] = T(0);
-    } else {
-      seam_sum<T, NC, TX, TY, TZ>(a, rs, m, qx, qy, qz, acc);
-    }
-#pragma unroll
-    for (int c = 0; c < NC; ++c) __builtin_nontemporal_store(acc[c], &yi[slot + c * a.n_local]);
-    return;
-  }
   // interface groups: each member's macro-local value (seam sum or the tile
   // kernel's store) goes to LDS; every member then adds its group's values in
   // ascending member order, so all copies receive the same sum

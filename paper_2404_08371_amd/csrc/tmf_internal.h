@@ -180,6 +180,9 @@ struct SeamInst {
 
 // largest tile-row table staged in LDS by the seam reduction (entries)
 constexpr int kSeamRowsLds = 8192;
+// seam points per thread of the seam reduction for scalar fields (vector
+// fields: 1); a seam work entry covers 256 times this many points
+constexpr int kSeamPointsPerThread = 4;
 
 // launchers (kernels.hip); return the HIP error of the launch
 template <typename T>

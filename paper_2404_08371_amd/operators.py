@@ -9,7 +9,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import check, lib
+from ._lib import check, lib, release
 
 P1_LAPLACE, P1_DIVKGRAD, P2_LAPLACE, P2_DIVKGRAD, P2V_EPSILON = range(5)
 F64, F32 = 0, 1
@@ -69,10 +69,8 @@ class Mesh:
         return out
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().tmf_mesh_destroy(h)
-            self._h = None
+        release(getattr(self, "_h", None), "tmf_mesh_destroy")
+        self._h = None
 
 
 def _stream_handle(device):
@@ -160,7 +158,5 @@ class Operator:
         return gx, gk
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().tmf_op_destroy(h)
-            self._h = None
+        release(getattr(self, "_h", None), "tmf_op_destroy")
+        self._h = None
