@@ -17,8 +17,10 @@ not on the domain boundary (a DoF is on the domain boundary when one of its
 copies lies on a macro face that belongs to a single macro-tetrahedron).
 
 Also: the same operator assembled as a sparse matrix (for brute-force
-checks), the gradient of L = 0.5 |A(k) x - b|^2 with respect to x and k, and
-plain conjugate gradients.
+checks), its diagonal (assembly of the matrix diagonal is the second
+operation the paper's generator provides, section "Code Generation for FEM
+on Hybrid Tetrahedral Grids"), the gradient of L = 0.5 |A(k) x - b|^2 with
+respect to x and k, and plain conjugate gradients.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -183,6 +185,21 @@ class Problem:
             ye = np.einsum("eji,ei->ej", A, xm[idx])
             y += np.bincount(idx.ravel(), weights=ye.ravel(), minlength=y.size)
         return self._mask(self.interface_sum(y))
+
+    # ---------------------------------------------------------- diagonal
+    def diagonal(self, coeff=None):
+        """diag(D A D) on every copy: each element's (A_T)_vv added into node v,
+        the copies of a DoF summed, boundary rows 0."""
+        if HAS_COEFF[self.kind]:
+            coeff = np.asarray(coeff, dtype=np.float64)
+        d = np.zeros(self.ncomp * self.n_local)
+        for m, tn, P, nodes in self.element_batches():
+            c_e = coeff[nodes] if HAS_COEFF[self.kind] else None
+            A = self.element_matrices(P, c_e, m)
+            idx = self._dof_index(nodes)
+            de = np.einsum("ejj->ej", A)
+            d += np.bincount(idx.ravel(), weights=de.ravel(), minlength=d.size)
+        return self._mask(self.interface_sum(d))
 
     # ------------------------------------------------------------ sparse
     def assemble(self, coeff=None):
