@@ -183,6 +183,18 @@ tmf_status tmf_apply_local(tmf_op *op, const void *coeff, const void *x, void *y
  * ascending slot order).  No-op on single-macro meshes. */
 tmf_status tmf_interface_sum(tmf_op *op, void *v, tmf_stream stream);
 
+/* d = diag(A(coeff)): the diagonal of the operator that tmf_apply applies
+ * (one of the operations the paper's generator provides besides the
+ * matrix-vector product, section "Code Generation for FEM on Hybrid
+ * Tetrahedral Grids"; its Conclusion names the inverse diagonal for
+ * smoothers).  d_i = sum over the micro-tets T containing DoF i of
+ * (A_T)_ii, summed over the copies of a shared DoF (every copy receives the
+ * total); with TMF_BC_DIRICHLET_ZERO the rows of boundary DoFs are 0, as in
+ * D A D.  coeff as for tmf_apply; d: n_local values of the op's precision
+ * (device), must not alias coeff.  Asynchronous on `stream`.  Kinds other
+ * than TMF_P2_LAPLACE and TMF_P2_DIVKGRAD return TMF_EUNSUPPORTED. */
+tmf_status tmf_diagonal(tmf_op *op, const void *coeff, void *d, tmf_stream stream);
+
 /* Reverse mode of the macro-local apply of TMF_P1_DIVKGRAD (FP64 or FP32).
  * With y = L(k) x the local apply (boundary masking included), given gy:
  *   gx = L(k)^T gy = L(k) gy,
@@ -241,6 +253,9 @@ tmf_status tmf_batch_apply(tmf_batch *batch, const void *coeff, const void *x, v
 /* tmf_batch_apply with events around the element kernel (see tmf_apply_timed). */
 tmf_status tmf_batch_apply_timed(tmf_batch *batch, const void *coeff, const void *x, void *y,
                                  const uint8_t *active, tmf_stream stream, void *ev_before, void *ev_after);
+/* d_i = diag(A_i(coeff_i)) for every instance (as tmf_diagonal), in one
+ * launch; scalar P2 kinds only. */
+tmf_status tmf_batch_diagonal(tmf_batch *batch, const void *coeff, void *d, tmf_stream stream);
 tmf_status tmf_batch_set_tile(tmf_batch *batch, int cfg);
 /* Autotuner over the tile shapes for the whole batch (as tmf_op_autotune). */
 tmf_status tmf_batch_autotune(tmf_batch *batch, const void *coeff, const void *x, void *y, tmf_stream stream,
@@ -251,11 +266,17 @@ tmf_status tmf_batch_autotune(tmf_batch *batch, const void *coeff, const void *x
  * FP64 (r = b - A x with the FP64 batch, norms, x += |r| d), inner
  * conjugate-gradient corrections A d = r / |r| with the FP32 batch and
  * FP64-accumulated dot products, started from d = 0 and stopped per instance
- * at |r_inner| <= inner_rtol |r_inner,0| or inner_maxit iterations.  Blocks of
+ * when r.r (r.z with the Jacobi preconditioner) has fallen to inner_rtol^2
+ * times its start value, or after inner_maxit iterations.  Blocks of
  * graph_iters inner iterations are captured once into a HIP graph and
  * replayed (use_graph = 0 runs the same kernels eagerly).  An instance stops
  * when |b - A x| <= tol |b| (2-norms over distinct DoFs). */
 typedef struct tmf_ir tmf_ir;
+/* Inner preconditioner: none, or Jacobi (z = D^-1 r with D = diag(A) of the
+ * FP64 operators, assembled by tmf_batch_diagonal at the start of each solve;
+ * Dirichlet rows, whose diagonal is 0, get 0).  With Jacobi the inner
+ * iteration is preconditioned CG and its stopping test uses r.z. */
+enum { TMF_PRECOND_NONE = 0, TMF_PRECOND_JACOBI = 1 };
 typedef struct {
   double tol;         /* outer relative residual, e.g. 1e-10 */
   int max_outer;      /* outer steps */
@@ -263,6 +284,7 @@ typedef struct {
   int inner_maxit;    /* inner iterations per outer step */
   int graph_iters;    /* inner iterations per graph launch */
   int use_graph;      /* 1: replay a captured HIP graph */
+  int precond;        /* TMF_PRECOND_NONE or TMF_PRECOND_JACOBI */
 } tmf_ir_options;
 typedef struct {
   int outer;           /* outer refinement steps taken */
@@ -273,8 +295,9 @@ typedef struct {
 } tmf_ir_stats;
 /* Both batches hold the same instances (same meshes and boundary conditions),
  * b64 in FP64 and b32 in FP32, scalar kinds only; opt may be NULL for the
- * defaults {1e-10, 30, 1e-4, 2000, 16, 1}.  Allocates the device workspace
- * (6 vectors of the batch length) and a private stream. */
+ * defaults {1e-10, 30, 1e-4, 2000, 16, 1, TMF_PRECOND_JACOBI}.  Allocates the
+ * device workspace (6 vectors of the batch length, 7 with Jacobi) and a
+ * private stream.  Jacobi needs a scalar P2 kind (TMF_EUNSUPPORTED otherwise). */
 tmf_status tmf_ir_create(tmf_batch *b64, tmf_batch *b32, const tmf_ir_options *opt, tmf_ir **out);
 void tmf_ir_destroy(tmf_ir *solver);
 /* Solve in place: x (device, FP64, initial guess on entry), b (device, FP64),

@@ -34,6 +34,7 @@ SIGNATURES = [
     ("tmf_apply_timed", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     ("tmf_apply_local", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     ("tmf_interface_sum", c_int, [c_vp, c_vp, c_vp]),
+    ("tmf_diagonal", c_int, [c_vp, c_vp, c_vp, c_vp]),
     ("tmf_op_num_tiles", c_int, [c_vp, ctypes.POINTER(c_int)]),
     ("tmf_op_tile_shape", c_int, [c_vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
                                   ctypes.POINTER(c_int)]),
@@ -46,6 +47,7 @@ SIGNATURES = [
     ("tmf_batch_info", c_int, [c_vp, ctypes.POINTER(c_int), c_i64p]),
     ("tmf_batch_apply", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     ("tmf_batch_apply_timed", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    ("tmf_batch_diagonal", c_int, [c_vp, c_vp, c_vp, c_vp]),
     ("tmf_batch_set_tile", c_int, [c_vp, c_int]),
     ("tmf_batch_autotune", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(c_int),
                                    ctypes.POINTER(ctypes.c_float)]),

@@ -8,9 +8,13 @@ from ._lib import check, lib, release
 from .operators import DTYPE, _stream_handle
 
 
+PRECOND_NONE, PRECOND_JACOBI = 0, 1
+
+
 class IROptions(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("inner_rtol", ctypes.c_double),
-                ("inner_maxit", ctypes.c_int), ("graph_iters", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("inner_maxit", ctypes.c_int), ("graph_iters", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("precond", ctypes.c_int)]
 
 
 class IRStats(ctypes.Structure):
@@ -66,6 +70,14 @@ class Batch:
         check(lib().tmf_batch_apply(self._h, pk, px, self._ptr(out, "out"), pa, _stream_handle(x.device)))
         return out
 
+    def diagonal(self, coeff=None, out=None):
+        """diag(A_i(coeff_i)) of every instance, concatenated (scalar P2 kinds)."""
+        pk = self._ptr(coeff, "coeff") if self.has_coeff else None
+        if out is None:
+            out = torch.empty(self.length, dtype=self.dtype, device=coeff.device if coeff is not None else "cuda")
+        check(lib().tmf_batch_diagonal(self._h, pk, self._ptr(out, "out"), _stream_handle(out.device)))
+        return out
+
     def set_tile(self, cfg):
         check(lib().tmf_batch_set_tile(self._h, int(cfg)))
 
@@ -87,9 +99,9 @@ class IRSolver:
     """FP64 iterative refinement around FP32 CG over a pair of batches (FP64, FP32)."""
 
     def __init__(self, b64, b32, tol=1e-10, max_outer=30, inner_rtol=1e-4, inner_maxit=2000, graph_iters=16,
-                 use_graph=True):
+                 use_graph=True, precond=PRECOND_JACOBI):
         self.b64, self.b32 = b64, b32
-        opt = IROptions(tol, max_outer, inner_rtol, inner_maxit, graph_iters, 1 if use_graph else 0)
+        opt = IROptions(tol, max_outer, inner_rtol, inner_maxit, graph_iters, 1 if use_graph else 0, int(precond))
         h = ctypes.c_void_p()
         check(lib().tmf_ir_create(b64.handle, b32.handle, ctypes.byref(opt), ctypes.byref(h)))
         self._h = h

@@ -42,7 +42,7 @@ struct tmf_ir {
   tmf_ir_options opt{};
   hipStream_t stream = nullptr;
   DevBuf<double> Ax, r64, part1, part2, scal;
-  DevBuf<float> r32, p, q, d;
+  DevBuf<float> r32, p, q, d, dinv;
   DevBuf<int> it;
   DevBuf<uint8_t> flags;
   BlasCtx ctx{};
@@ -58,14 +58,16 @@ struct tmf_ir {
 
 namespace {
 
+// mode: the batch's kind, or a diagonal mode of the element kernel.  Every
+// entry of an active instance is written by the element kernel or the seam
+// reduction; inactive instances are set to zero if zero_inactive (the
+// solver's own applies skip that: its vector kernels never read them).
 template <typename T>
-hipError_t batch_apply_t(tmf_batch *b, const void *coeff, const void *x, void *y, const uint8_t *active,
-                         hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+hipError_t batch_apply_t(tmf_batch *b, int mode, const void *coeff, const void *x, void *y, const uint8_t *active,
+                         hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, bool zero_inactive) {
   T *yy = static_cast<T *>(y);
   hipError_t e = hipSuccess;
-  // every entry of an active instance is written by the element kernel or the
-  // seam reduction; inactive instances are left at zero
-  if (active) e = launch_fill<T>(yy, b->off[b->count], T(0), s);
+  if (active && zero_inactive) e = launch_fill<T>(yy, b->off[b->count], T(0), s);
   if (e != hipSuccess) return e;
   TileArgs<T> a;
   a.inst = reinterpret_cast<const InstDesc<T> *>(b->desc.p);
@@ -78,7 +80,7 @@ hipError_t batch_apply_t(tmf_batch *b, const void *coeff, const void *x, void *y
   a.x = static_cast<const T *>(x);
   a.y = yy;
   if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
-  e = launch_tile_apply<T>(a, b->kind, TMF_MAP_AFFINE, b->tile_cfg, s);
+  e = launch_tile_apply<T>(a, mode, TMF_MAP_AFFINE, b->tile_cfg, s);
   if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
   if (e != hipSuccess) return e;
   // seam and interface reduction of every instance, one launch
@@ -88,10 +90,23 @@ hipError_t batch_apply_t(tmf_batch *b, const void *coeff, const void *x, void *y
 }
 
 tmf_status batch_apply(tmf_batch *b, const void *coeff, const void *x, void *y, const uint8_t *active,
-                       hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
-  hipError_t e = b->prec == TMF_F64 ? batch_apply_t<double>(b, coeff, x, y, active, s, ev0, ev1)
-                                    : batch_apply_t<float>(b, coeff, x, y, active, s, ev0, ev1);
+                       hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool zero_inactive = true) {
+  hipError_t e = b->prec == TMF_F64
+                     ? batch_apply_t<double>(b, b->kind, coeff, x, y, active, s, ev0, ev1, zero_inactive)
+                     : batch_apply_t<float>(b, b->kind, coeff, x, y, active, s, ev0, ev1, zero_inactive);
   if (e != hipSuccess) return hip_fail(e, "batch apply launch");
+  return TMF_OK;
+}
+
+tmf_status batch_diagonal(tmf_batch *b, const void *coeff, void *d, hipStream_t s) {
+  if (b->kind != TMF_P2_LAPLACE && b->kind != TMF_P2_DIVKGRAD)
+    return fail(TMF_EUNSUPPORTED, "the diagonal is provided for the scalar P2 kinds");
+  const int mode = b->kind == TMF_P2_LAPLACE ? P2_LAPLACE_DIAG : P2_DIVKGRAD_DIAG;
+  // the diagonal modes read no x; the output pointer stands in for it
+  hipError_t e = b->prec == TMF_F64
+                     ? batch_apply_t<double>(b, mode, coeff, d, d, nullptr, s, nullptr, nullptr, true)
+                     : batch_apply_t<float>(b, mode, coeff, d, d, nullptr, s, nullptr, nullptr, true);
+  if (e != hipSuccess) return hip_fail(e, "batch diagonal launch");
   return TMF_OK;
 }
 
@@ -241,6 +256,15 @@ tmf_status tmf_batch_apply_timed(tmf_batch *b, const void *coeff, const void *x,
                      static_cast<hipEvent_t>(ev_after));
 }
 
+tmf_status tmf_batch_diagonal(tmf_batch *b, const void *coeff, void *d, tmf_stream stream) {
+  if (!b || !d) return fail(TMF_EINVAL, "batch or d is NULL");
+  if (has_coeff(b->kind) != (coeff != nullptr))
+    return fail(TMF_EINVAL, has_coeff(b->kind) ? "this operator needs a coefficient field"
+                                               : "this operator takes no coefficient field");
+  if (coeff && d == coeff) return fail(TMF_EINVAL, "d must not alias the coefficient");
+  return batch_diagonal(b, coeff, d, static_cast<hipStream_t>(stream));
+}
+
 tmf_status tmf_batch_set_tile(tmf_batch *b, int cfg) {
   if (!b) return fail(TMF_EINVAL, "batch is NULL");
   const int nt = b->kind == TMF_P2V_EPSILON ? 1 : kNumTileCfg;
@@ -297,7 +321,7 @@ tmf_status tmf_batch_autotune(tmf_batch *b, const void *coeff, const void *x, vo
 namespace {
 
 tmf_status inner_step(tmf_ir *S, const void *k32, hipStream_t s) {
-  tmf_status st = batch_apply(S->b32, k32, S->p.p, S->q.p, S->ctx.sc.iact, s);
+  tmf_status st = batch_apply(S->b32, k32, S->p.p, S->q.p, S->ctx.sc.iact, s, nullptr, nullptr, false);
   if (st != TMF_OK) return st;
   hipError_t e = blas_cg_step_after_apply(S->ctx, S->d.p, S->r32.p, S->p.p, S->q.p, S->part1.p,
                                           S->opt.inner_rtol * S->opt.inner_rtol, S->opt.inner_maxit, s);
@@ -346,9 +370,12 @@ tmf_status tmf_ir_create(tmf_batch *b64, tmf_batch *b32, const tmf_ir_options *o
     if (b64->ops[i]->mesh != b32->ops[i]->mesh || b64->ops[i]->bc != b32->ops[i]->bc)
       return fail(TMF_EINVAL, "instance %d differs between the batches", i);
   if (b64->ncomp != 1) return fail(TMF_EUNSUPPORTED, "the solver handles scalar operators");
-  tmf_ir_options o = opt ? *opt : tmf_ir_options{1e-10, 30, 1e-4, 2000, 16, 1};
-  if (!(o.tol > 0) || o.max_outer < 1 || !(o.inner_rtol > 0) || o.inner_maxit < 1 || o.graph_iters < 1)
+  tmf_ir_options o = opt ? *opt : tmf_ir_options{1e-10, 30, 1e-4, 2000, 16, 1, TMF_PRECOND_JACOBI};
+  if (!(o.tol > 0) || o.max_outer < 1 || !(o.inner_rtol > 0) || o.inner_maxit < 1 || o.graph_iters < 1 ||
+      (o.precond != TMF_PRECOND_NONE && o.precond != TMF_PRECOND_JACOBI))
     return fail(TMF_EINVAL, "bad solver options");
+  if (o.precond == TMF_PRECOND_JACOBI && b64->kind != TMF_P2_LAPLACE && b64->kind != TMF_P2_DIVKGRAD)
+    return fail(TMF_EUNSUPPORTED, "the Jacobi preconditioner needs a scalar P2 kind");
   auto *S = new (std::nothrow) tmf_ir;
   if (!S) return fail(TMF_ENOMEM, "host allocation failed");
   S->b64 = b64;
@@ -362,6 +389,7 @@ tmf_status tmf_ir_create(tmf_batch *b64, tmf_batch *b32, const tmf_ir_options *o
   if (st == TMF_OK) st = S->p.alloc(n);
   if (st == TMF_OK) st = S->q.alloc(n);
   if (st == TMF_OK) st = S->d.alloc(n);
+  if (st == TMF_OK && o.precond == TMF_PRECOND_JACOBI) st = S->dinv.alloc(n);
   if (st == TMF_OK) st = S->part1.alloc(b64->nchunks);
   if (st == TMF_OK) st = S->part2.alloc(b64->nchunks);
   if (st == TMF_OK) st = S->scal.alloc(6 * static_cast<size_t>(c));
@@ -389,6 +417,7 @@ tmf_status tmf_ir_create(tmf_batch *b64, tmf_batch *b32, const tmf_ir_options *o
   x.first = b64->first.p;
   x.count = c;
   x.owner = b64->owner.p;
+  x.dinv = o.precond == TMF_PRECOND_JACOBI ? S->dinv.p : nullptr;
   x.sc.rnorm = S->scal.p;
   x.sc.bnorm = S->scal.p + c;
   x.sc.rr = S->scal.p + 2 * c;
@@ -421,6 +450,14 @@ tmf_status tmf_ir_solve(tmf_ir *S, const double *coeff64, const float *coeff32, 
   if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
   (void)hipEventDestroy(ev);
   if (e != hipSuccess) return hip_fail(e, "stream ordering");
+  // Jacobi: the inverse diagonal of the FP64 operators for these coefficients
+  // (the FP64 residual buffer serves as scratch for the diagonal)
+  if (S->opt.precond == TMF_PRECOND_JACOBI) {
+    tmf_status sd = batch_diagonal(S->b64, coeff64, S->Ax.p, s);
+    if (sd != TMF_OK) return sd;
+    e = blas_inverse_diagonal(S->ctx, S->Ax.p, S->dinv.p, s);
+    if (e != hipSuccess) return hip_fail(e, "inverse diagonal");
+  }
   std::vector<uint8_t> flags(2 * c);
   std::vector<double> norms(2 * c);
   std::vector<int> its(c);

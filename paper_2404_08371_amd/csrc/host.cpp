@@ -657,6 +657,35 @@ GroupArgs group_args(const tmf_op *op) {
   return g;
 }
 
+// P2 and epsilon: element kernel (mode `kind`: an operator kind or a diagonal
+// mode), then the seam reduction, with the interface sums unless a
+// macro-local result is asked for
+template <typename T>
+hipError_t tile_path(tmf_op *op, int kind, const void *coeff, const void *x, T *yy, hipStream_t s, hipEvent_t ev0,
+                     hipEvent_t ev1, bool interface) {
+  hipError_t e;
+  TileArgs<T> a;
+  a.inst = reinterpret_cast<const InstDesc<T> *>(op->desc.p);
+  a.tiles = op->tiles[op->tile_cfg].p;
+  a.ntiles = op->ntiles[op->tile_cfg];
+  a.active = nullptr;
+  a.qtab = reinterpret_cast<const T *>(op->qtab.p);
+  a.nq = op->nq;
+  a.k = static_cast<const T *>(coeff);
+  a.x = static_cast<const T *>(x);
+  a.y = yy;
+  if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
+  e = launch_tile_apply<T>(a, kind, op->mesh->map, op->tile_cfg, s);
+  if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
+  const int c = op->tile_cfg;
+  if (e == hipSuccess)
+    e = launch_seam_gather<T>(reinterpret_cast<const SeamInst<T> *>(op->seaminst[c].p),
+                              op->seamwork[c].p + (interface ? 0 : op->ngroupwork[c]),
+                              interface ? op->nseamwork[c] : op->nseamonly[c], yy, nullptr, interface ? 0 : 1,
+                              op->ncomp, c, seam_rows_lds(op->seamrows[c]), s);
+  return e;
+}
+
 template <typename T>
 hipError_t apply_t(tmf_op *op, const void *coeff, const void *x, void *y, hipStream_t s,
                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool interface = true) {
@@ -673,27 +702,7 @@ hipError_t apply_t(tmf_op *op, const void *coeff, const void *x, void *y, hipStr
     e = launch_p1_apply<T>(a, op->kind, op->chunks.p, op->nchunks, s);
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
   } else {
-    TileArgs<T> a;
-    a.inst = reinterpret_cast<const InstDesc<T> *>(op->desc.p);
-    a.tiles = op->tiles[op->tile_cfg].p;
-    a.ntiles = op->ntiles[op->tile_cfg];
-    a.active = nullptr;
-    a.qtab = reinterpret_cast<const T *>(op->qtab.p);
-    a.nq = op->nq;
-    a.k = static_cast<const T *>(coeff);
-    a.x = static_cast<const T *>(x);
-    a.y = yy;
-    if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
-    e = launch_tile_apply<T>(a, op->kind, op->mesh->map, op->tile_cfg, s);
-    if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
-    // seam reduction, with the interface sums unless a macro-local result is asked for
-    const int c = op->tile_cfg;
-    if (e == hipSuccess)
-      e = launch_seam_gather<T>(reinterpret_cast<const SeamInst<T> *>(op->seaminst[c].p),
-                                op->seamwork[c].p + (interface ? 0 : op->ngroupwork[c]),
-                                interface ? op->nseamwork[c] : op->nseamonly[c], yy, nullptr, interface ? 0 : 1,
-                                op->ncomp, c, seam_rows_lds(op->seamrows[c]), s);
-    return e;
+    return tile_path<T>(op, op->kind, coeff, x, yy, s, ev0, ev1, interface);
   }
   if (e != hipSuccess || !interface) return e;
   return launch_interface_sum<T>(group_args(op), yy, s);
@@ -749,6 +758,24 @@ tmf_status tmf_apply_local(tmf_op *op, const void *coeff, const void *x, void *y
   hipError_t e = op->prec == TMF_F64 ? apply_t<double>(op, coeff, x, y, s, nullptr, nullptr, false)
                                      : apply_t<float>(op, coeff, x, y, s, nullptr, nullptr, false);
   if (e != hipSuccess) return hip_fail(e, "apply launch");
+  return TMF_OK;
+}
+
+tmf_status tmf_diagonal(tmf_op *op, const void *coeff, void *d, tmf_stream stream) {
+  if (!op || !d) return fail(TMF_EINVAL, "op or d is NULL");
+  if (op->kind != TMF_P2_LAPLACE && op->kind != TMF_P2_DIVKGRAD)
+    return fail(TMF_EUNSUPPORTED, "the diagonal is provided for the scalar P2 kinds");
+  if (has_coeff(op->kind) != (coeff != nullptr))
+    return fail(TMF_EINVAL, has_coeff(op->kind) ? "this operator needs a coefficient field"
+                                                : "this operator takes no coefficient field");
+  if (coeff && d == coeff) return fail(TMF_EINVAL, "d must not alias the coefficient");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int dk = op->kind == TMF_P2_LAPLACE ? P2_LAPLACE_DIAG : P2_DIVKGRAD_DIAG;
+  // the diagonal modes read no x; the output pointer stands in for it
+  hipError_t e = op->prec == TMF_F64
+                     ? tile_path<double>(op, dk, coeff, d, static_cast<double *>(d), s, nullptr, nullptr, true)
+                     : tile_path<float>(op, dk, coeff, d, static_cast<float *>(d), s, nullptr, nullptr, true);
+  if (e != hipSuccess) return hip_fail(e, "diagonal launch");
   return TMF_OK;
 }
 

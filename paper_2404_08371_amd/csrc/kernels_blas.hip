@@ -6,7 +6,13 @@
 // writes one FP64 partial (fixed tree order inside the workgroup), and a
 // second pass adds an instance's partials in chunk order.  CG scalars live
 // per instance in device memory; an instance whose inner iteration has
-// converged keeps its vectors unchanged (alpha = 0 and p frozen).
+// converged keeps its vectors unchanged (alpha = 0 and p frozen), and its q
+// is never read (the solver's applies skip inactive instances).
+//
+// With a Jacobi preconditioner (dinv = 1 / diag(A), 0 on Dirichlet rows) the
+// inner iteration is preconditioned CG: z = dinv r is formed on the fly where
+// it is used, rr holds r.z, and the inner stopping test compares r.z with its
+// initial value.
 #include "solver_internal.h"
 
 namespace tmf {
@@ -88,10 +94,11 @@ __global__ void k_outer_norms(const double *prr, const double *pbb, const int *f
   s.oact[i] = (rn > tol * bn) ? 1 : 0;
 }
 
-// r32 = r64 / |r| for active instances (0 otherwise), p = r32, d = 0; partial r32.r32
+// r32 = r64 / |r| for active instances (0 otherwise), p = z = dinv r32, d = 0;
+// partial r32.z
 __global__ __launch_bounds__(kBlasThreads) void k_scale_cast(const double *r64, float *r32, float *p, float *d,
-                                                              const uint8_t *owner, const ChunkDesc *ch,
-                                                              CgScalars s, double *partial) {
+                                                              const float *dinv, const uint8_t *owner,
+                                                              const ChunkDesc *ch, CgScalars s, double *partial) {
   __shared__ double sh[kBlasThreads];
   const ChunkDesc c = ch[blockIdx.x];
   const bool act = s.oact[c.inst] != 0;
@@ -100,10 +107,11 @@ __global__ __launch_bounds__(kBlasThreads) void k_scale_cast(const double *r64, 
   for (int i = threadIdx.x; i < c.len; i += kBlasThreads) {
     const int64_t g = c.start + i;
     const float v = act ? float(r64[g] * inv) : 0.0f;
+    const float z = dinv ? dinv[g] * v : v;
     r32[g] = v;
-    p[g] = v;
+    p[g] = z;
     d[g] = 0.0f;
-    if (owner == nullptr || owner[g]) acc += double(v) * double(v);
+    if (owner == nullptr || owner[g]) acc += double(v) * double(z);
   }
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = acc;
@@ -129,12 +137,17 @@ __global__ void k_cg_alpha(const double *partial, const int *first, int count, C
   s.alpha[i] = (s.iact[i] && pq > 0) ? s.rr[i] / pq : 0.0;
 }
 
-// d += alpha p, r -= alpha q; partial r.r
+// d += alpha p, r -= alpha q; partial r.z.  A chunk whose instance takes no
+// step (alpha = 0) is left alone: its q was not computed.
 __global__ __launch_bounds__(kBlasThreads) void k_cg_update(float *d, float *r, const float *p, const float *q,
-                                                             const uint8_t *owner, const ChunkDesc *ch,
-                                                             CgScalars s, double *partial) {
+                                                             const float *dinv, const uint8_t *owner,
+                                                             const ChunkDesc *ch, CgScalars s, double *partial) {
   __shared__ double sh[kBlasThreads];
   const ChunkDesc c = ch[blockIdx.x];
+  if (s.alpha[c.inst] == 0.0) {
+    if (threadIdx.x == 0) partial[blockIdx.x] = 0.0;
+    return;
+  }
   const float a = float(s.alpha[c.inst]);
   double acc = 0;
   for (int i = threadIdx.x; i < c.len; i += kBlasThreads) {
@@ -142,7 +155,8 @@ __global__ __launch_bounds__(kBlasThreads) void k_cg_update(float *d, float *r, 
     const float rv = r[g] - a * q[g];
     d[g] += a * p[g];
     r[g] = rv;
-    if (owner == nullptr || owner[g]) acc += double(rv) * double(rv);
+    const float z = dinv ? dinv[g] * rv : rv;
+    if (owner == nullptr || owner[g]) acc += double(rv) * double(z);
   }
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = acc;
@@ -166,15 +180,25 @@ __global__ void k_cg_beta(const double *partial, const int *first, int count, do
   s.iact[i] = (rrn > rtol2 * s.rr0[i] && it < maxit) ? 1 : 0;
 }
 
-// p = r + beta p for instances that took the step
-__global__ __launch_bounds__(kBlasThreads) void k_cg_p(float *p, const float *r, const ChunkDesc *ch,
-                                                        CgScalars s) {
+// p = z + beta p (z = dinv r) for instances that took the step
+__global__ __launch_bounds__(kBlasThreads) void k_cg_p(float *p, const float *r, const float *dinv,
+                                                        const ChunkDesc *ch, CgScalars s) {
   const ChunkDesc c = ch[blockIdx.x];
   if (s.alpha[c.inst] == 0.0) return;
   const float b = float(s.beta[c.inst]);
   for (int i = threadIdx.x; i < c.len; i += kBlasThreads) {
     const int64_t g = c.start + i;
-    p[g] = r[g] + b * p[g];
+    const float z = dinv ? dinv[g] * r[g] : r[g];
+    p[g] = z + b * p[g];
+  }
+}
+
+// dinv = 1 / d where d > 0 (0 on Dirichlet rows, whose diagonal is 0)
+__global__ __launch_bounds__(kBlasThreads) void k_inv_diag(const double *d, float *dinv, const ChunkDesc *ch) {
+  const ChunkDesc c = ch[blockIdx.x];
+  for (int i = threadIdx.x; i < c.len; i += kBlasThreads) {
+    const int64_t g = c.start + i;
+    dinv[g] = d[g] > 0.0 ? float(1.0 / d[g]) : 0.0f;
   }
 }
 
@@ -208,7 +232,7 @@ hipError_t blas_residual(const BlasCtx &c, const double *b, const double *Ax, do
 
 hipError_t blas_start_inner(const BlasCtx &c, const double *r64, float *r32, float *p, float *d, double *part,
                             hipStream_t s) {
-  TMF_LAUNCH(k_scale_cast, c.nchunks, kBlasThreads, s, r64, r32, p, d, c.owner, c.chunks, c.sc, part);
+  TMF_LAUNCH(k_scale_cast, c.nchunks, kBlasThreads, s, r64, r32, p, d, c.dinv, c.owner, c.chunks, c.sc, part);
   TMF_LAUNCH(k_cg_init, c.count, 64, s, part, c.first, c.count, c.sc);
   return hipSuccess;
 }
@@ -217,9 +241,14 @@ hipError_t blas_cg_step_after_apply(const BlasCtx &c, float *d, float *r, float 
                                     double rtol2, int maxit, hipStream_t s) {
   TMF_LAUNCH((k_dot_partial<float, float>), c.nchunks, kBlasThreads, s, p, q, c.owner, c.chunks, part);
   TMF_LAUNCH(k_cg_alpha, c.count, 64, s, part, c.first, c.count, c.sc);
-  TMF_LAUNCH(k_cg_update, c.nchunks, kBlasThreads, s, d, r, p, q, c.owner, c.chunks, c.sc, part);
+  TMF_LAUNCH(k_cg_update, c.nchunks, kBlasThreads, s, d, r, p, q, c.dinv, c.owner, c.chunks, c.sc, part);
   TMF_LAUNCH(k_cg_beta, c.count, 64, s, part, c.first, c.count, rtol2, maxit, c.sc);
-  TMF_LAUNCH(k_cg_p, c.nchunks, kBlasThreads, s, p, r, c.chunks, c.sc);
+  TMF_LAUNCH(k_cg_p, c.nchunks, kBlasThreads, s, p, r, c.dinv, c.chunks, c.sc);
+  return hipSuccess;
+}
+
+hipError_t blas_inverse_diagonal(const BlasCtx &c, const double *d, float *dinv, hipStream_t s) {
+  TMF_LAUNCH(k_inv_diag, c.nchunks, kBlasThreads, s, d, dinv, c.chunks);
   return hipSuccess;
 }
 

@@ -154,6 +154,21 @@ __device__ inline void p2_elem(const T u[10], const T kv[10], CPtr<T> Gp, T y[10
   }
 }
 
+// Diagonal of the local matrix: entry v is (A_T e_v)_v.  The unit vectors
+// are compile-time constants, so the unrolled calls fold to the terms that
+// touch node v (and the coefficient weights are formed once).
+template <typename T, bool HASK>
+__device__ inline void p2_diag(const T kv[10], CPtr<T> Gp, T d[10]) {
+#pragma unroll
+  for (int v = 0; v < 10; ++v) {
+    T u[10], y[10];
+#pragma unroll
+    for (int w = 0; w < 10; ++w) u[w] = w == v ? T(1) : T(0);
+    p2_elem<T, HASK>(u, kv, Gp, y);
+    d[v] = y[v];
+  }
+}
+
 // Fused local apply of int 2 mu eps(u):eps(v) on one affine tet.
 //   component gradients: grad u_c = sum_a lambda_a g^c_a
 //   strain at vertex a: E_a = sym(G_a), row c of G_a = g^c_a
@@ -327,7 +342,9 @@ struct TileCfg {
   static_assert(RXP >= OO + TX && (2 * RXP - TX) % 16 == 0, "row pitch");
   static constexpr int C = TX * TY * TZ;
   static constexpr int NC = KIND == P2V_EPSILON ? 3 : 1;
-  static constexpr bool HASK = KIND != P2_LAPLACE;
+  static constexpr bool HASK = KIND != P2_LAPLACE && KIND != P2_LAPLACE_DIAG;
+  // diagonal mode: no x is staged, each micro-tet adds its local diagonal
+  static constexpr bool DIAG = KIND == P2_LAPLACE_DIAG || KIND == P2_DIVKGRAD_DIAG;
   // Scalar kinds: WPG wavefronts per workgroup, wavefront w applying the
   // micro-tet types t = w (mod WPG) to every cube of the box, so the type is
   // a compile-time constant inside each loop (LDS node offsets become
@@ -376,6 +393,14 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
     for (int v = 0; v < 10; ++v)
 #pragma unroll
       for (int c = 0; c < 3; ++c) atomicAdd(&sy[c][li[v]], double(y[c][v]));
+  } else if constexpr (KIND == P2_LAPLACE_DIAG || KIND == P2_DIVKGRAD_DIAG) {
+    constexpr bool HASK = KIND == P2_DIVKGRAD_DIAG;
+    T kv[10], d[10];
+#pragma unroll
+    for (int v = 0; v < 10; ++v) kv[v] = HASK ? sk[li[v]] : T(1);
+    p2_diag<T, HASK>(kv, cptr(g->Gp), d);
+#pragma unroll
+    for (int v = 0; v < 10; ++v) atomicAdd(&sy[0][li[v]], double(d[v]));
   } else {
     constexpr bool HASK = KIND != P2_LAPLACE;
     T u[10], kv[10], y[10];
@@ -500,7 +525,7 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
       if (qi <= lim) {
         const int off = srb[row] + qi;
         const int zp = (qi == lim) | ((qi == 0) << 1) | (info & 12);
-        if (!((bnd >> zp) & 1u)) {
+        if (!Cfg::DIAG && !((bnd >> zp) & 1u)) {
 #pragma unroll
           for (int c = 0; c < NC; ++c) xv[p][c] = xb[c][off];
         }
@@ -770,6 +795,8 @@ hipError_t launch_tile_apply(const TileArgs<T> &a, int kind, int map, int cfg, h
   switch (kind) {
     case P2_LAPLACE: return launch_kind<T, P2_LAPLACE, 0>(a, cfg, s);
     case P2_DIVKGRAD: return launch_kind<T, P2_DIVKGRAD, 0>(a, cfg, s);
+    case P2_LAPLACE_DIAG: return launch_kind<T, P2_LAPLACE_DIAG, 0>(a, cfg, s);
+    case P2_DIVKGRAD_DIAG: return launch_kind<T, P2_DIVKGRAD_DIAG, 0>(a, cfg, s);
     case P2V_EPSILON:
       // the epsilon tiles stage 3 components; only the smallest tile fits LDS twice per CU
       if (cfg != 0) return hipErrorInvalidValue;

@@ -29,6 +29,7 @@ struct BlasCtx {
   const int *first;      // count + 1 chunk offsets per instance
   int count;
   const uint8_t *owner;  // NULL when every slot is the only copy of its DoF
+  const float *dinv;     // Jacobi preconditioner 1 / diag(A) (0 on Dirichlet rows), or NULL for none
   CgScalars sc;
 };
 
@@ -39,5 +40,7 @@ hipError_t blas_start_inner(const BlasCtx &c, const double *r64, float *r32, flo
 hipError_t blas_cg_step_after_apply(const BlasCtx &c, float *d, float *r, float *p, const float *q, double *part,
                                     double rtol2, int maxit, hipStream_t s);
 hipError_t blas_update_x(const BlasCtx &c, double *x, const float *d, hipStream_t s);
+// dinv = 1 / d where d > 0, else 0 (FP64 diagonal in, FP32 out)
+hipError_t blas_inverse_diagonal(const BlasCtx &c, const double *d, float *dinv, hipStream_t s);
 
 }  // namespace tmf

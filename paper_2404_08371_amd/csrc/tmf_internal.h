@@ -82,6 +82,8 @@ __host__ __device__ inline int zero_pattern(int i, int j, int k, int N) {
 }
 
 enum Kind { P1_LAPLACE = 0, P1_DIVKGRAD = 1, P2_LAPLACE = 2, P2_DIVKGRAD = 3, P2V_EPSILON = 4 };
+// element-kernel modes that assemble diag(A) of a scalar P2 kind instead of applying it
+enum DiagKind { P2_LAPLACE_DIAG = 5, P2_DIVKGRAD_DIAG = 6 };
 
 template <typename T>
 struct LatticeArgs {

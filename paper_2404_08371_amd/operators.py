@@ -137,6 +137,18 @@ class Operator:
             check(lib().tmf_apply_local(self._h, pk, px, py, _stream_handle(x.device)))
         return out
 
+    def diagonal(self, coeff=None, out=None):
+        """diag(A(coeff)) in the macro-local layout, every copy holding the total (scalar P2 kinds)."""
+        pk = self._vec(coeff, "coeff", 1) if self.has_coeff else None
+        if not self.has_coeff and coeff is not None:
+            raise ValueError("this operator takes no coefficient")
+        if out is None:
+            out = torch.empty(self.n_local, dtype=self.dtype, device=coeff.device if coeff is not None else "cuda")
+        pd = self._vec(out, "out", 1)
+        with torch.cuda.device(out.device):
+            check(lib().tmf_diagonal(self._h, pk, pd, _stream_handle(out.device)))
+        return out
+
     def interface_sum_(self, v):
         """In place: every copy of a shared DoF gets the sum over its copies."""
         pv = self._vec(v, "v", self.ncomp)

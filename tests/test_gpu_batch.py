@@ -9,7 +9,8 @@
   the oracle's own CG solution: |x - x_ref| / |x_ref| <= cond * 1e-10 with a
   bound of 1e-7 used for these small, well-conditioned instances.
 * The graph-replayed inner iteration and the eager one give the same result
-  to the solver tolerance.
+  to the solver tolerance, with the Jacobi-preconditioned inner iteration
+  (the default) and without a preconditioner.
 """
 import numpy as np
 import pytest
@@ -61,9 +62,10 @@ def test_batch_equals_single_applies():
     assert 0 <= cfg < 4 and ms > 0
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_iterative_refinement_reaches_fp64_residual(use_graph):
-    print("ir case graph", use_graph, flush=True)
+@pytest.mark.parametrize("use_graph,precond", [(True, T.PRECOND_JACOBI), (False, T.PRECOND_JACOBI),
+                                               (True, T.PRECOND_NONE)])
+def test_iterative_refinement_reaches_fp64_residual(use_graph, precond):
+    print("ir case graph", use_graph, "precond", precond, flush=True)
     levels = [2, 3, 4, 3, 2, 4]
     inst = make_instances(levels)
     ops64 = [T.Operator(m, T.P2_DIVKGRAD, T.F64) for m, _, _ in inst]
@@ -78,7 +80,7 @@ def test_iterative_refinement_reaches_fp64_residual(use_graph):
     K64 = b64.concat(ks)
     B = b64.apply(b64.concat(xstar), K64)
     X = torch.zeros_like(B)
-    solver = T.IRSolver(b64, b32, tol=1e-10, use_graph=use_graph, graph_iters=8)
+    solver = T.IRSolver(b64, b32, tol=1e-10, use_graph=use_graph, graph_iters=8, precond=precond)
     stats, rel = solver.solve(B, X, K64, K64.float())
     print("stats", stats, "relres", rel.max())
     assert stats["converged"] and rel.max() <= 1e-10
