@@ -662,7 +662,7 @@ GroupArgs group_args(const tmf_op *op) {
 // macro-local result is asked for
 template <typename T>
 hipError_t tile_path(tmf_op *op, int kind, const void *coeff, const void *x, T *yy, hipStream_t s, hipEvent_t ev0,
-                     hipEvent_t ev1, bool interface) {
+                     hipEvent_t ev1, bool interface, const void *x2 = nullptr, int seam_flags = 0) {
   hipError_t e;
   TileArgs<T> a;
   a.inst = reinterpret_cast<const InstDesc<T> *>(op->desc.p);
@@ -673,6 +673,7 @@ hipError_t tile_path(tmf_op *op, int kind, const void *coeff, const void *x, T *
   a.nq = op->nq;
   a.k = static_cast<const T *>(coeff);
   a.x = static_cast<const T *>(x);
+  a.x2 = static_cast<const T *>(x2);
   a.y = yy;
   if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
   e = launch_tile_apply<T>(a, kind, op->mesh->map, op->tile_cfg, s);
@@ -681,7 +682,8 @@ hipError_t tile_path(tmf_op *op, int kind, const void *coeff, const void *x, T *
   if (e == hipSuccess)
     e = launch_seam_gather<T>(reinterpret_cast<const SeamInst<T> *>(op->seaminst[c].p),
                               op->seamwork[c].p + (interface ? 0 : op->ngroupwork[c]),
-                              interface ? op->nseamwork[c] : op->nseamonly[c], yy, nullptr, interface ? 0 : 1,
+                              interface ? op->nseamwork[c] : op->nseamonly[c], yy, nullptr,
+                              (interface ? 0 : kSeamLocal) | seam_flags,
                               op->ncomp, c, seam_rows_lds(op->seamrows[c]), s);
   return e;
 }
@@ -711,6 +713,15 @@ hipError_t apply_t(tmf_op *op, const void *coeff, const void *x, void *y, hipStr
 template <typename T>
 hipError_t adjoint_t(tmf_op *op, const void *coeff, const void *x, const void *gy, void *gx, void *gk,
                      hipStream_t s) {
+  if (op->kind == TMF_P2_DIVKGRAD) {
+    // gx = L(k) gy: the macro-local apply; gk: the coefficient-gradient mode
+    // of the element kernel, reduced per copy, Dirichlet k-nodes kept
+    hipError_t e = tile_path<T>(op, op->kind, coeff, gy, static_cast<T *>(gx), s, nullptr, nullptr, false);
+    if (e == hipSuccess && gk)
+      e = tile_path<T>(op, P2_DIVKGRAD_GRADK, nullptr, x, static_cast<T *>(gk), s, nullptr, nullptr, false, gy,
+                       kSeamKeepBoundary);
+    return e;
+  }
   P1AdjArgs<T> a;
   a.lat = lattice_args<T>(op);
   a.k = static_cast<const T *>(coeff);
@@ -868,8 +879,8 @@ tmf_status tmf_op_autotune(tmf_op *op, const void *coeff, const void *x, void *y
 tmf_status tmf_apply_adjoint(tmf_op *op, const void *coeff, const void *x, const void *gy, void *gx, void *gk,
                              tmf_stream stream) {
   if (!op) return fail(TMF_EINVAL, "op is NULL");
-  if (op->kind != TMF_P1_DIVKGRAD)
-    return fail(TMF_EUNSUPPORTED, "the fused adjoint is implemented for TMF_P1_DIVKGRAD");
+  if (op->kind != TMF_P1_DIVKGRAD && op->kind != TMF_P2_DIVKGRAD)
+    return fail(TMF_EUNSUPPORTED, "the adjoint is implemented for the div(k grad) kinds");
   if (!coeff || !x || !gy || !gx) return fail(TMF_EINVAL, "coeff, x, gy and gx are required");
   const void *ins[3] = {coeff, x, gy};
   for (const void *p : ins)

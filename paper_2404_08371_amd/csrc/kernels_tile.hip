@@ -169,6 +169,58 @@ __device__ inline void p2_diag(const T kv[10], CPtr<T> Gp, T d[10]) {
   }
 }
 
+// Coefficient gradient of the local div(k grad) form: A_T(k) is linear in the
+// 10 nodal values of k, so gk_b = gy . A_T(e_b) u.  Writing the apply as
+// y = Y(sigma), sigma[e][d] = sum_c W[c][e] h[c][d] (see p2_elem), gives
+// gy . y = sum_{c,e} W[c][e] M[c][e] with M[c][e] = sum_d h[c][d] Gam[e][d],
+// where Gam collects the coefficients of gy . Y(sigma) in sigma; then
+// gk_b = sum_{c,e} W(e_b)[c][e] M[c][e] with the constant weights W(e_b).
+template <typename T>
+__device__ inline void p2_gradk(const T u[10], const T g[10], CPtr<T> Gp, T gk[10]) {
+  T sp[4][3];
+  grad_coeffs(u, sp);
+  T h[4][4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int d = 1; d < 4; ++d)
+      h[c][d] = sp[c][0] * Gp[4 * 1 + d] + sp[c][1] * Gp[4 * 2 + d] + sp[c][2] * Gp[4 * 3 + d];
+    h[c][0] = -(h[c][1] + h[c][2] + h[c][3]);
+  }
+  // gy . Y(sigma) = sum_b g_b (4 sigma[b][b] - sum_e sigma[e][b])
+  //               + sum_edges (b,c) 4 g_bc (sigma[c][b] + sigma[b][c])
+  T gam[4][4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) gam[e][b] = -g[b] + (e == b ? T(4) * g[b] : T(0));
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int b = kEdge[e][0], c = kEdge[e][1];
+    gam[c][b] += T(4) * g[4 + e];
+    gam[b][c] += T(4) * g[4 + e];
+  }
+  T M[4][4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      M[c][e] = h[c][0] * gam[e][0] + h[c][1] * gam[e][1] + h[c][2] * gam[e][2] + h[c][3] * gam[e][3];
+#pragma unroll
+  for (int b = 0; b < 10; ++b) {
+    T kb[10], Wb[4][4];
+#pragma unroll
+    for (int w = 0; w < 10; ++w) kb[w] = w == b ? T(1) : T(0);
+    weights_p2(kb, Wb);
+    T acc = T(0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc += Wb[c][e] * M[c][e];
+    gk[b] = acc;
+  }
+}
+
 // Fused local apply of int 2 mu eps(u):eps(v) on one affine tet.
 //   component gradients: grad u_c = sum_a lambda_a g^c_a
 //   strain at vertex a: E_a = sym(G_a), row c of G_a = g^c_a
@@ -341,10 +393,15 @@ struct TileCfg {
   static_assert(TX == 4 || TX == 8, "row pitch chosen for TX = 4 or 8");
   static_assert(RXP >= OO + TX && (2 * RXP - TX) % 16 == 0, "row pitch");
   static constexpr int C = TX * TY * TZ;
-  static constexpr int NC = KIND == P2V_EPSILON ? 3 : 1;
-  static constexpr bool HASK = KIND != P2_LAPLACE && KIND != P2_LAPLACE_DIAG;
+  static constexpr int NC = KIND == P2V_EPSILON ? 3 : 1;  // output components
   // diagonal mode: no x is staged, each micro-tet adds its local diagonal
   static constexpr bool DIAG = KIND == P2_LAPLACE_DIAG || KIND == P2_DIVKGRAD_DIAG;
+  // coefficient-gradient mode: x and gy staged (both masked), no coefficient;
+  // the output gk is not zeroed on Dirichlet DoFs (boundary values of k act
+  // on interior rows)
+  static constexpr bool GRADK = KIND == P2_DIVKGRAD_GRADK;
+  static constexpr int NCI = GRADK ? 2 : NC;  // staged input vectors
+  static constexpr bool HASK = KIND != P2_LAPLACE && KIND != P2_LAPLACE_DIAG && !GRADK;
   // Scalar kinds: WPG wavefronts per workgroup, wavefront w applying the
   // micro-tet types t = w (mod WPG) to every cube of the box, so the type is
   // a compile-time constant inside each loop (LDS node offsets become
@@ -393,6 +450,16 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
     for (int v = 0; v < 10; ++v)
 #pragma unroll
       for (int c = 0; c < 3; ++c) atomicAdd(&sy[c][li[v]], double(y[c][v]));
+  } else if constexpr (KIND == P2_DIVKGRAD_GRADK) {
+    T u[10], gv[10], gk[10];
+#pragma unroll
+    for (int v = 0; v < 10; ++v) {
+      u[v] = sx[0][li[v]];
+      gv[v] = sx[1][li[v]];
+    }
+    p2_gradk<T>(u, gv, cptr(g->Gp), gk);
+#pragma unroll
+    for (int v = 0; v < 10; ++v) atomicAdd(&sy[0][li[v]], double(gk[v]));
   } else if constexpr (KIND == P2_LAPLACE_DIAG || KIND == P2_DIVKGRAD_DIAG) {
     constexpr bool HASK = KIND == P2_DIVKGRAD_DIAG;
     T kv[10], d[10];
@@ -459,10 +526,10 @@ __device__ __forceinline__ void type_loop(const TileArgs<T> &a, const InstDesc<T
 template <typename T, int KIND, int MAP, int TX, int TY, int TZ>
 __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_tile(TileArgs<T> a) {
   using Cfg = TileCfg<T, KIND, MAP, TX, TY, TZ>;
-  constexpr int RX = Cfg::RX, RY = Cfg::RY, R = Cfg::R, NC = Cfg::NC, NTH = Cfg::NTH;
+  constexpr int RX = Cfg::RX, RY = Cfg::RY, R = Cfg::R, NC = Cfg::NC, NCI = Cfg::NCI, NTH = Cfg::NTH;
   constexpr int OO = Cfg::OO, RXP = Cfg::RXP, RP = Cfg::RP;
   constexpr bool HASK = Cfg::HASK;
-  __shared__ T sx[NC][RP];
+  __shared__ T sx[NCI][RP];
   // the element results are accumulated in FP64 in both precisions: FP64
   // LDS atomics run at full speed on gfx950 where FP32 ones stall the LDS
   // pipeline, and the partial sums of a point keep 53-bit mantissas
@@ -499,26 +566,25 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
     sri[row] = (lim << 8) | ((qj == 0) << 2) | ((qk == 0) << 3) | ((ey && ez) << 4);
   }
   __syncthreads();
-  const T *xb[NC];
+  const T *xb[NCI];
   T *yb[NC];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    xb[c] = a.x + base + c * nl;
-    yb[c] = a.y + base + c * nl;
-  }
+  for (int c = 0; c < NCI; ++c) xb[c] = (Cfg::GRADK && c == 1 ? a.x2 : a.x + c * nl) + base;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) yb[c] = a.y + base + c * nl;
   const T *kb = HASK ? a.k + base : nullptr;
 
   // 1. stage the box: x with Dirichlet DoFs zeroed, and the coefficient.  The
   // loop is unrolled over a thread's points so that all its loads are in
   // flight together (one memory latency per tile instead of one per point).
   constexpr int PF = (R + NTH - 1) / NTH;
-  T xv[PF][NC], kv[PF];
+  T xv[PF][NCI], kv[PF];
 #pragma unroll
   for (int p = 0; p < PF; ++p) {
     const int r = tid + p * NTH;
     kv[p] = T(0);
 #pragma unroll
-    for (int c = 0; c < NC; ++c) xv[p][c] = T(0);
+    for (int c = 0; c < NCI; ++c) xv[p][c] = T(0);
     if (r < R) {
       const int row = r / RX, rx = r - row * RX;
       const int info = sri[row], lim = info >> 8, qi = 2 * bx0 + rx;
@@ -527,7 +593,7 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
         const int zp = (qi == lim) | ((qi == 0) << 1) | (info & 12);
         if (!Cfg::DIAG && !((bnd >> zp) & 1u)) {
 #pragma unroll
-          for (int c = 0; c < NC; ++c) xv[p][c] = xb[c][off];
+          for (int c = 0; c < NCI; ++c) xv[p][c] = xb[c][off];
         }
         if (HASK) kv[p] = kb[off];
       }
@@ -540,10 +606,9 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
       const int row = r / RX, rx = r - row * RX;
       const int sl = lds_slot(rx, row, OO, RXP);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        sx[c][sl] = xv[p][c];
-        sy[c][sl] = 0.0;
-      }
+      for (int c = 0; c < NCI; ++c) sx[c][sl] = xv[p][c];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) sy[c][sl] = 0.0;
       if (HASK) sk[sl] = kv[p];
     }
   }
@@ -588,7 +653,7 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
     const bool excl = ((info >> 4) & 1) && ((rx & 1) || ((rx > 0 || bx0 == 0) && rx < 2 * TX));
     const int sl = lds_slot(rx, row, OO, RXP);
     if (excl) {
-      const bool dir = (bnd >> zp) & 1u;
+      const bool dir = !Cfg::GRADK && ((bnd >> zp) & 1u);
       const int off = srb[row] + qi;
 #pragma unroll
       for (int c = 0; c < NC; ++c) __builtin_nontemporal_store(dir ? T(0) : T(sy[c][sl]), &yb[c][off]);
@@ -664,8 +729,9 @@ struct SeamPPT {
 // larger table is read from global memory).
 template <typename T, int NC, int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) void k_seam(const SeamInst<T> *__restrict__ insts, const int4 *__restrict__ work,
-                                              T *__restrict__ y, const uint8_t *__restrict__ active, int local,
+                                              T *__restrict__ y, const uint8_t *__restrict__ active, int flags,
                                               int rows_lds) {
+  const bool local = flags & kSeamLocal;
   constexpr int PPT = SeamPPT<NC>::value;
   extern __shared__ int srs[];
   __shared__ T sv[NC][256];
@@ -712,7 +778,8 @@ __global__ __launch_bounds__(256) void k_seam(const SeamInst<T> *__restrict__ in
     // macro-local result is asked for)
     // every point's loads first, then the stores (the compiler cannot move a
     // load of one point above the store of another: y and the partials may alias)
-    const uint32_t bm = a.dirichlet ? a.bnd[m] : 0u, sh = local ? 0u : a.shared[m];
+    const uint32_t bm = a.dirichlet && !(flags & kSeamKeepBoundary) ? a.bnd[m] : 0u;
+    const uint32_t sh = local ? 0u : a.shared[m];
     T acc[PPT][NC];
     int64_t sl[PPT];
     bool wr[PPT], dz[PPT];
@@ -737,7 +804,7 @@ __global__ __launch_bounds__(256) void k_seam(const SeamInst<T> *__restrict__ in
   const int pk = pks[0];
   const int qx = pk & 1023, qy = (pk >> 10) & 1023, qz = pk >> 20;
   const int z = zero_pattern(qx, qy, qz, a.N);
-  const bool dir = a.dirichlet && ((a.bnd[m] >> z) & 1u);
+  const bool dir = a.dirichlet && !(flags & kSeamKeepBoundary) && ((a.bnd[m] >> z) & 1u);
   // interface groups: each member's macro-local value (seam sum or the tile
   // kernel's store) goes to LDS; every member then adds its group's values in
   // ascending member order, so all copies receive the same sum
@@ -797,6 +864,7 @@ hipError_t launch_tile_apply(const TileArgs<T> &a, int kind, int map, int cfg, h
     case P2_DIVKGRAD: return launch_kind<T, P2_DIVKGRAD, 0>(a, cfg, s);
     case P2_LAPLACE_DIAG: return launch_kind<T, P2_LAPLACE_DIAG, 0>(a, cfg, s);
     case P2_DIVKGRAD_DIAG: return launch_kind<T, P2_DIVKGRAD_DIAG, 0>(a, cfg, s);
+    case P2_DIVKGRAD_GRADK: return launch_kind<T, P2_DIVKGRAD_GRADK, 0>(a, cfg, s);
     case P2V_EPSILON:
       // the epsilon tiles stage 3 components; only the smallest tile fits LDS twice per CU
       if (cfg != 0) return hipErrorInvalidValue;
@@ -811,20 +879,20 @@ template hipError_t launch_tile_apply<float>(const TileArgs<float> &, int, int, 
 
 template <typename T>
 hipError_t launch_seam_gather(const SeamInst<T> *inst, const int4 *work, int nwork, T *y, const uint8_t *active,
-                              int local, int ncomp, int cfg, int rows_lds, hipStream_t s) {
+                              int flags, int ncomp, int cfg, int rows_lds, hipStream_t s) {
   if (nwork == 0) return hipSuccess;
   const dim3 grid(nwork);
   const size_t sh = static_cast<size_t>(rows_lds) * sizeof(int);
   if (ncomp == 3) {
     if (cfg != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_seam<T, 3, 4, 4, 4>), grid, dim3(256), sh, s, inst, work, y, active, local, rows_lds);
+    hipLaunchKernelGGL((k_seam<T, 3, 4, 4, 4>), grid, dim3(256), sh, s, inst, work, y, active, flags, rows_lds);
     return hipGetLastError();
   }
   switch (cfg) {
-    case 0: hipLaunchKernelGGL((k_seam<T, 1, 4, 4, 4>), grid, dim3(256), sh, s, inst, work, y, active, local, rows_lds); break;
-    case 1: hipLaunchKernelGGL((k_seam<T, 1, 8, 4, 2>), grid, dim3(256), sh, s, inst, work, y, active, local, rows_lds); break;
-    case 2: hipLaunchKernelGGL((k_seam<T, 1, 8, 4, 4>), grid, dim3(256), sh, s, inst, work, y, active, local, rows_lds); break;
-    case 3: hipLaunchKernelGGL((k_seam<T, 1, 4, 4, 8>), grid, dim3(256), sh, s, inst, work, y, active, local, rows_lds); break;
+    case 0: hipLaunchKernelGGL((k_seam<T, 1, 4, 4, 4>), grid, dim3(256), sh, s, inst, work, y, active, flags, rows_lds); break;
+    case 1: hipLaunchKernelGGL((k_seam<T, 1, 8, 4, 2>), grid, dim3(256), sh, s, inst, work, y, active, flags, rows_lds); break;
+    case 2: hipLaunchKernelGGL((k_seam<T, 1, 8, 4, 4>), grid, dim3(256), sh, s, inst, work, y, active, flags, rows_lds); break;
+    case 3: hipLaunchKernelGGL((k_seam<T, 1, 4, 4, 8>), grid, dim3(256), sh, s, inst, work, y, active, flags, rows_lds); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -82,8 +82,9 @@ __host__ __device__ inline int zero_pattern(int i, int j, int k, int N) {
 }
 
 enum Kind { P1_LAPLACE = 0, P1_DIVKGRAD = 1, P2_LAPLACE = 2, P2_DIVKGRAD = 3, P2V_EPSILON = 4 };
-// element-kernel modes that assemble diag(A) of a scalar P2 kind instead of applying it
-enum DiagKind { P2_LAPLACE_DIAG = 5, P2_DIVKGRAD_DIAG = 6 };
+// element-kernel modes besides the applies: diag(A) of a scalar P2 kind, and
+// the coefficient gradient gk_b = gy . (dA/dk_b) x of P2 div(k grad)
+enum KernelMode { P2_LAPLACE_DIAG = 5, P2_DIVKGRAD_DIAG = 6, P2_DIVKGRAD_GRADK = 7 };
 
 template <typename T>
 struct LatticeArgs {
@@ -140,6 +141,7 @@ struct TileArgs {
   int nq;
   const T *k;
   const T *x;
+  const T *x2 = nullptr;  // second staged input (gy of the coefficient-gradient mode)
   T *y;
 };
 
@@ -193,9 +195,13 @@ template <typename T>
 hipError_t launch_p1_adjoint(const P1AdjArgs<T> &a, const int4 *chunks, int nchunks, hipStream_t s);
 template <typename T>
 hipError_t launch_tile_apply(const TileArgs<T> &a, int kind, int map, int tile_cfg, hipStream_t s);
+// flags: kSeamLocal (macro-local result: no interface sums, shared points
+// reduced within their macro), kSeamKeepBoundary (Dirichlet DoFs keep their
+// sums instead of 0)
+constexpr int kSeamLocal = 1, kSeamKeepBoundary = 2;
 template <typename T>
 hipError_t launch_seam_gather(const SeamInst<T> *inst, const int4 *work, int nwork, T *y, const uint8_t *active,
-                              int local, int ncomp, int tile_cfg, int rows_lds, hipStream_t s);
+                              int flags, int ncomp, int tile_cfg, int rows_lds, hipStream_t s);
 template <typename T>
 hipError_t launch_interface_sum(const GroupArgs &g, T *y, hipStream_t s);
 template <typename T>

@@ -157,7 +157,7 @@ class Operator:
         return v
 
     def adjoint(self, coeff, x, gy, gx=None, gk=None, want_gk=True):
-        """Reverse mode of the macro-local apply of P1 div(k grad): returns (gx, gk)."""
+        """Reverse mode of the macro-local apply of the div(k grad) kinds (P1, P2): returns (gx, gk)."""
         pk, px, pg = self._vec(coeff, "coeff", 1), self._vec(x, "x", 1), self._vec(gy, "gy", 1)
         if gx is None:
             gx = torch.empty_like(x)

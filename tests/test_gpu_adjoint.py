@@ -1,4 +1,11 @@
-"""GPU reverse mode of the P1 div(k grad) operator (hand-written adjoint kernel).
+"""GPU reverse mode of the div(k grad) operators (hand-written adjoint kernels).
+
+P2 div(k grad) (the same checks, below the P1 ones): reference tet at level 5
+and the 6-macro Kuhn cube at level 3 against the oracle's gradients; 16
+central-difference directions each for x and k; FP32 against FP64; and
+d/dk (w . A(k) x) . dk = w . (A(k + dk) x - A(k) x) on the cube (A linear in k).
+
+P1 div(k grad):
 
 Workload: one macro tet (the reference tetrahedron) at level 7 (366,145
 DoFs), k = 1 + 0.9 U[-1,1) per node, x and b ~ U[-1,1), Dirichlet rows and
@@ -136,3 +143,82 @@ def test_backward_is_the_transpose_of_the_forward_map():
     # A is linear in k: d/dk (w . A(k) x) . dk = w . (A(k + dk) x - A(k) x)
     lin = (w * (op.apply(x.detach(), k.detach() + dk) - op.apply(x.detach(), k.detach()))).sum().item()
     assert abs((k.grad * dk).sum().item() - lin) <= 1e-11 * max(abs(lin), 1.0)
+
+
+# ------------------------------------------------------------------ P2
+def setup_p2(level, mesh="ref", prec=T.F64):
+    v, t = W.meshes.ref_tet() if mesh == "ref" else W.meshes.kuhn_cube()
+    m = T.Mesh(v, t, level)
+    op = T.Operator(m, T.P2_DIVKGRAD, prec, T.BC_DIRICHLET_ZERO)
+    info = m.dof_info(2)
+    keys = info["keys"]
+    return m, op, info, W.fields.perturbed_k(keys, 5), W.uniform_from_keys(6, keys), W.uniform_from_keys(7, keys)
+
+
+@pytest.mark.parametrize("level,mesh", [(5, "ref"), (3, "cube")])
+def test_p2_gradients_match_oracle(level, mesh):
+    print("p2 adjoint oracle case", level, mesh, flush=True)
+    m, op, info, k, x, b = setup_p2(level, mesh)
+    L, gx, gk = loss_and_grads(op, k, x, b, info["owner"])
+    v, t = W.meshes.ref_tet() if mesh == "ref" else W.meshes.kuhn_cube()
+    pr = O.Problem(v, t, level, O.P2_DIVKGRAD, O.BC_DIRICHLET_ZERO)
+    ko, xo, bo = (W.fields.perturbed_k(pr.keys, 5), W.uniform_from_keys(6, pr.keys),
+                  W.uniform_from_keys(7, pr.keys))
+    Lo, gxo, gko = pr.loss_gradients(ko, xo, bo)
+    assert abs(L - Lo) <= 1e-12 * abs(Lo)
+    for g, go in ((gx, gxo), (gk, gko)):
+        tot = np.zeros(pr.n_unique)
+        np.add.at(tot, pr.uid, g)
+        assert np.linalg.norm(tot - pr.to_unique(go)) <= 1e-12 * np.linalg.norm(go), mesh
+
+
+def test_p2_central_differences():
+    print("p2 adjoint FD case", flush=True)
+    m, op, info, k, x, b = setup_p2(5)
+    L, gx, gk = loss_and_grads(op, k, x, b, info["owner"])
+    kt, xt, bt = (torch.tensor(a, device="cuda") for a in (k, x, b))
+
+    def loss(xv, kv):
+        y = op.apply(xv, kv)
+        return 0.5 * float(((y - bt) ** 2).sum())
+
+    rng = np.random.default_rng(9)
+    h = 1e-6
+    for which in ("x", "k"):
+        for _ in range(16):
+            d = rng.uniform(-1, 1, x.size)
+            d /= np.linalg.norm(d)
+            dt = torch.tensor(d, device="cuda")
+            if which == "x":
+                fd = (loss(xt + h * dt, kt) - loss(xt - h * dt, kt)) / (2 * h)
+                an = float(gx @ d)
+            else:
+                fd = (loss(xt, kt + h * dt) - loss(xt, kt - h * dt)) / (2 * h)
+                an = float(gk @ d)
+            assert abs(fd - an) / max(abs(an), 1e-3 * L) <= 1e-6, (which, fd, an)
+
+
+def test_p2_adjoint_fp32_matches_fp64():
+    m, op, info, k, x, b = setup_p2(4)
+    op32 = T.Operator(m, T.P2_DIVKGRAD, T.F32, T.BC_DIRICHLET_ZERO)
+    gy = torch.tensor(b, device="cuda")
+    gx64, gk64 = op.adjoint(torch.tensor(k, device="cuda"), torch.tensor(x, device="cuda"), gy)
+    gx32, gk32 = op32.adjoint(torch.tensor(k, device="cuda", dtype=torch.float32),
+                              torch.tensor(x, device="cuda", dtype=torch.float32), gy.float())
+    for a64, a32 in ((gx64, gx32), (gk64, gk32)):
+        a64, a32 = a64.cpu().numpy(), a32.double().cpu().numpy()
+        assert np.abs(a64 - a32).max() <= 2e-5 * np.abs(a64).max()
+
+
+def test_p2_coefficient_gradient_is_the_linear_part():
+    v, t = W.meshes.kuhn_cube()
+    op = T.Operator(T.Mesh(v, t, 2), T.P2_DIVKGRAD, T.F64)
+    info = op.mesh.dof_info(2)
+    k = torch.tensor(W.fields.perturbed_k(info["keys"], 5), device="cuda", requires_grad=True)
+    x = torch.tensor(W.uniform_from_keys(1, info["keys"]), device="cuda")
+    w = torch.tensor(W.uniform_from_keys(2, info["keys"]), device="cuda")
+    (TmfApply.apply(x, k, op) * w).sum().backward()
+    dk = torch.tensor(np.random.default_rng(4).uniform(-1, 1, op.n_local), device="cuda")
+    lin = (w * (op.apply(x, k.detach() + dk) - op.apply(x, k.detach()))).sum().item()
+    assert abs((k.grad * dk).sum().item() - lin) <= 1e-11 * max(abs(lin), 1.0)
+
