@@ -2,7 +2,8 @@
 """Benchmark: matrix-free finite-element operator apply on one MI355X.
 
 Headline workload (one "step" = one operator application y = A(k) x, the
-whole apply path: zero fill, element kernel, interface sum, boundary mask):
+whole apply path: element kernel with boundary masking, then the seam and
+interface reduction):
 the P2 variable-coefficient diffusion operator -div(k grad) (equation P2V) in
 FP64 on the unit cube split into 6 macro-tetrahedra, refinement level 6
 (2,146,689 DoFs), k = 1 + 0.5 sin(2 pi x) cos(2 pi y) z interpolated at the
@@ -11,8 +12,10 @@ rows and columns.  Inputs are resident in HBM before timing starts.
 
 Also reported under "forms": the other operators and precisions on their
 workloads (P1 Laplacian at levels 4 and 9, the P1 div(k grad) forward and
-fused adjoint at levels 7 and 9, the P2 FP32 apply, the vector epsilon
-operator on the radially blended shell in FP64 and FP32).
+fused adjoint at levels 7 and 9, the P2 FP32 apply, the P2 FP64 apply at
+level 7, the P2 div(k grad) adjoint on the headline workload, the vector
+epsilon operator on the radially blended shell in FP64 and FP32) and the
+batched FP32-in-FP64 refinement solve (Jacobi-preconditioned and plain).
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
 """
@@ -41,6 +44,8 @@ FLOPS = {
     "p1_laplace": 30,          # per DoF: 15-point stencil
     "p1_divkgrad": 312,        # per DoF: 24 incident micro-tets x (4x4 row, mean k, accumulate)
     "p1_adjoint": 1200,        # per DoF: forward row (312) + 24 x bilinear form (37)
+    "p2_adjoint": 946,         # per micro-tet: forward apply of gy (358) + coefficient gradient (588:
+                               # gradient coefficients 40, h 72, Gam 44, M 112, 10 x 16-term contractions 320)
     "eps_affine": 970,         # per micro-tet
     "eps_blended_per_q": 657,  # per micro-tet and quadrature point (map Jacobian, inverse, 2 x 90-term contractions)
 }
@@ -385,6 +390,12 @@ def main():
         form("p2_divkgrad_fp64_cube_l7", m7, o7, "p2_divkgrad", 2, n_elements(6, 7) * FLOPS["p2_divkgrad"],
              24 * o7.n_local, PEAK_FP64, args.form_steps)
         del o7, m7
+        # P2 adjoint (gx = L(k) gy and gk), two element launches + two seam reductions;
+        # 48 B per slot (gy, k -> gx; x, gy -> gk)
+        o6a = T.Operator(mesh, T.P2_DIVKGRAD, T.F64)
+        form("p2_divkgrad_adjoint_fp64_cube_l6", mesh, o6a, "p2_divkgrad", 2, nel * FLOPS["p2_adjoint"],
+             48 * o6a.n_local, PEAK_FP64, args.form_steps, adjoint=True)
+        del o6a
         vs, ts = W.meshes.octahedral_shell()
         ms6 = T.Mesh(vs, ts, 6, T.MAP_SHELL_RADIAL)
         rule = W.quadrature.rule_degree5()
