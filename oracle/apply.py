@@ -240,14 +240,27 @@ class Problem:
         """g_k = d (gy . A(k) x) / dk for each unique coefficient DoF, on every copy.
 
         A(k) is linear in k, so g_k[m] = sum over elements T containing node m of
-        (D gy)_T . (dA_T/dk_m) (D x)_T.
+        (D gy)_T . (dA_T/dk_m) (D x)_T (for the epsilon operator k is mu and
+        dA_T/dmu_b = A_T(e_b), vector components included).
         """
-        if self.kind not in (P1_DIVKGRAD, P2_DIVKGRAD):
-            raise ValueError("coefficient gradient is defined for the div(k grad) operators")
+        if self.kind not in (P1_DIVKGRAD, P2_DIVKGRAD, P2V_EPSILON):
+            raise ValueError("coefficient gradient is defined for the div(k grad) and epsilon operators")
         coeff = np.asarray(coeff, dtype=np.float64)
         xm, rm = self._mask(np.asarray(x, float)), self._mask(np.asarray(gy, float))
         g = np.zeros(self.n_local)
         for m, tn, P, nodes in self.element_batches():
+            if self.kind == P2V_EPSILON:
+                # A_T(mu) is linear in the 10 nodal values of mu: dA_T/dmu_b = A_T(e_b)
+                idx = self._dof_index(nodes)
+                xe, re = xm[idx], rm[idx]
+                ge = np.empty(nodes.shape)
+                for b in range(nodes.shape[1]):
+                    eb = np.zeros(nodes.shape)
+                    eb[:, b] = 1.0
+                    Ab = self.element_matrices(P, eb, m)
+                    ge[:, b] = np.einsum("ej,eji,ei->e", re, Ab, xe)
+                g += np.bincount(nodes.ravel(), weights=ge.ravel(), minlength=g.size)
+                continue
             xe, re = xm[nodes], rm[nodes]
             if self.kind == P1_DIVKGRAD:
                 K = el.p1_laplace(P)
@@ -259,7 +272,9 @@ class Problem:
                 T = np.einsum("eab,mijab->emji", G, el.P2_CM)
                 ge = vol[:, None] * np.einsum("ej,emji,ei->em", re, T, xe)
             g += np.bincount(nodes.ravel(), weights=ge.ravel(), minlength=g.size)
-        return self.interface_sum(g)
+        # the coefficient is a scalar field: sum its copies
+        tot = np.bincount(self.uid, weights=g, minlength=self.n_unique)
+        return tot[self.uid]
 
     def loss_gradients(self, coeff, x, b):
         """L = 0.5 |A(k) x - b|^2 over unique DoFs: returns (L, dL/dx, dL/dk) on every copy."""

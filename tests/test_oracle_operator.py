@@ -214,6 +214,54 @@ def test_loss_gradients_central_differences(kind):
             assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * L)
 
 
+def _eps_problem(mesh):
+    if mesh == "cube":
+        v, t = W.meshes.kuhn_cube()
+        return O.Problem(v, t, 1, O.P2V_EPSILON, O.BC_DIRICHLET_ZERO)
+    v, t = W.meshes.octahedral_shell()
+    qb, qw = W.quadrature.rule_degree5()
+    return O.Problem(v, t, 0, O.P2V_EPSILON, O.BC_DIRICHLET_ZERO, map_=O.MAP_SHELL_RADIAL, qbary=qb, qw=qw)
+
+
+@pytest.mark.parametrize("mesh", ["cube", "shell"])
+def test_epsilon_mu_gradient_brute_force(mesh):
+    """A(mu) is linear in mu: gy . (A(mu + e_m) - A(mu)) x equals the gradient at m exactly (affine and blended)."""
+    pr = _eps_problem(mesh)
+    rng = np.random.default_rng(1)
+    x = pr.to_local(rng.standard_normal(3 * pr.n_unique))
+    gy = pr.to_local(rng.standard_normal(3 * pr.n_unique))
+    mu = 1 + 0.5 * np.sin(pr.xyz @ np.array([1.0, 2.0, 3.0]))
+    g = pr.coeff_gradient(mu, x, gy)
+    gu = np.zeros(pr.n_unique)
+    gu[pr.uid] = g
+    assert np.array_equal(g, gu[pr.uid])  # consistent over copies
+    base = pr.to_unique(gy) @ pr.to_unique(pr.apply(x, mu))
+    for m in rng.choice(pr.n_unique, 12, replace=False):
+        e = np.zeros(pr.n_unique)
+        e[m] = 1
+        d = pr.to_unique(gy) @ pr.to_unique(pr.apply(x, mu + e[pr.uid])) - base
+        assert abs(gu[m] - d) < 1e-11 * max(1, abs(base)), m
+
+
+def test_epsilon_loss_gradient_central_differences():
+    pr = _eps_problem("shell")
+    mu = W.fields.shell_mu(pr.keys, pr.xyz, 3)
+    x = pr.to_local(np.random.default_rng(2).uniform(-1, 1, 3 * pr.n_unique))
+    b = pr.to_local(np.random.default_rng(3).uniform(-1, 1, 3 * pr.n_unique))
+    L, gx, gk = pr.loss_gradients(mu, x, b)
+    rng = np.random.default_rng(4)
+    h = 1e-6
+    for _ in range(6):
+        du = rng.uniform(-1, 1, pr.n_unique)
+        du /= np.linalg.norm(du)
+        Lp = pr.loss_gradients(mu + h * du[pr.uid], x, b)[0]
+        Lm = pr.loss_gradients(mu - h * du[pr.uid], x, b)[0]
+        gu = np.zeros(pr.n_unique)
+        gu[pr.uid] = gk
+        an = gu @ du
+        assert abs((Lp - Lm) / (2 * h) - an) <= 1e-6 * max(abs(an), 1e-3 * L)
+
+
 def test_cg_matches_sparse_direct_solve():
     v, t = W.meshes.ref_tet()
     pr = O.Problem(v, t, 3, O.P2_DIVKGRAD, O.BC_DIRICHLET_ZERO)
