@@ -195,20 +195,21 @@ tmf_status tmf_interface_sum(tmf_op *op, void *v, tmf_stream stream);
  * than TMF_P2_LAPLACE and TMF_P2_DIVKGRAD return TMF_EUNSUPPORTED. */
 tmf_status tmf_diagonal(tmf_op *op, const void *coeff, void *d, tmf_stream stream);
 
-/* Reverse mode of the macro-local apply of TMF_P1_DIVKGRAD and
- * TMF_P2_DIVKGRAD (FP64 or FP32).
+/* Reverse mode of the macro-local apply of TMF_P1_DIVKGRAD, TMF_P2_DIVKGRAD
+ * and TMF_P2V_EPSILON (FP64 or FP32; for epsilon k is mu, and x, gy, gx hold
+ * 3 * n_local values while coeff and gk hold n_local).
  * With y = L(k) x the local apply (boundary masking included), given gy:
  *   gx = L(k)^T gy = L(k) gy,
  *   gk_m = gy . (dL/dk_m) x   for every coefficient slot m (copy by copy;
  *          not zeroed on Dirichlet DoFs, whose k values act on interior rows),
  * gk written only if non-NULL.  The transpose of the full apply y = S L(k) x
  * is therefore: tmf_interface_sum on (a copy of) dL/dy, then this call.  For
- * a single macro S = I.  All pointers are device arrays of n_local values; gx
- * and gk must not alias each other or any input.  P1: one fused launch.  P2:
- * gx is the macro-local apply of gy, gk a second element-kernel launch
- * (L is linear in the nodal k, so gk_m = gy . L(e_m) x, formed per
- * micro-tet from the gradients of x and gy).  Other kinds return
- * TMF_EUNSUPPORTED. */
+ * a single macro S = I.  All pointers are device arrays; gx and gk must not
+ * alias each other or any input.  P1: one fused launch.  P2
+ * and epsilon: gx is the macro-local apply of gy, gk a second
+ * element-kernel launch (L is linear in the nodal k, so gk_m = gy . L(e_m) x,
+ * formed per micro-tet from the gradients or strains of x and gy; on the
+ * blended shell per quadrature point).  Other kinds return TMF_EUNSUPPORTED. */
 tmf_status tmf_apply_adjoint(tmf_op *op, const void *coeff, const void *x, const void *gy,
                              void *gx, void *gk, tmf_stream stream);
 

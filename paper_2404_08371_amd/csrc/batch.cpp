@@ -86,7 +86,7 @@ hipError_t batch_apply_t(tmf_batch *b, int mode, const void *coeff, const void *
   // seam and interface reduction of every instance, one launch
   const int c = b->tile_cfg;
   return launch_seam_gather<T>(reinterpret_cast<const SeamInst<T> *>(b->seaminst[c].p), b->seamwork[c].p,
-                               b->nseamwork[c], yy, active, 0, b->ncomp, c, b->seamrows[c], s);
+                               b->nseamwork[c], yy, active, 0, b->ncomp, seam_ppt(b->ops[0]), c, b->seamrows[c], s);
 }
 
 tmf_status batch_apply(tmf_batch *b, const void *coeff, const void *x, void *y, const uint8_t *active,

@@ -662,7 +662,8 @@ GroupArgs group_args(const tmf_op *op) {
 // macro-local result is asked for
 template <typename T>
 hipError_t tile_path(tmf_op *op, int kind, const void *coeff, const void *x, T *yy, hipStream_t s, hipEvent_t ev0,
-                     hipEvent_t ev1, bool interface, const void *x2 = nullptr, int seam_flags = 0) {
+                     hipEvent_t ev1, bool interface, const void *x2 = nullptr, int seam_flags = 0,
+                     int ncomp_out = 0) {
   hipError_t e;
   TileArgs<T> a;
   a.inst = reinterpret_cast<const InstDesc<T> *>(op->desc.p);
@@ -684,7 +685,7 @@ hipError_t tile_path(tmf_op *op, int kind, const void *coeff, const void *x, T *
                               op->seamwork[c].p + (interface ? 0 : op->ngroupwork[c]),
                               interface ? op->nseamwork[c] : op->nseamonly[c], yy, nullptr,
                               (interface ? 0 : kSeamLocal) | seam_flags,
-                              op->ncomp, c, seam_rows_lds(op->seamrows[c]), s);
+                              ncomp_out ? ncomp_out : op->ncomp, seam_ppt(op), c, seam_rows_lds(op->seamrows[c]), s);
   return e;
 }
 
@@ -713,13 +714,15 @@ hipError_t apply_t(tmf_op *op, const void *coeff, const void *x, void *y, hipStr
 template <typename T>
 hipError_t adjoint_t(tmf_op *op, const void *coeff, const void *x, const void *gy, void *gx, void *gk,
                      hipStream_t s) {
-  if (op->kind == TMF_P2_DIVKGRAD) {
+  if (op->kind == TMF_P2_DIVKGRAD || op->kind == TMF_P2V_EPSILON) {
     // gx = L(k) gy: the macro-local apply; gk: the coefficient-gradient mode
-    // of the element kernel, reduced per copy, Dirichlet k-nodes kept
+    // of the element kernel (a scalar field), reduced per copy, Dirichlet
+    // coefficient nodes kept
     hipError_t e = tile_path<T>(op, op->kind, coeff, gy, static_cast<T *>(gx), s, nullptr, nullptr, false);
+    const int mode = op->kind == TMF_P2_DIVKGRAD ? P2_DIVKGRAD_GRADK : P2V_EPSILON_GRADMU;
     if (e == hipSuccess && gk)
-      e = tile_path<T>(op, P2_DIVKGRAD_GRADK, nullptr, x, static_cast<T *>(gk), s, nullptr, nullptr, false, gy,
-                       kSeamKeepBoundary);
+      e = tile_path<T>(op, mode, nullptr, x, static_cast<T *>(gk), s, nullptr, nullptr, false, gy, kSeamKeepBoundary,
+                       1);
     return e;
   }
   P1AdjArgs<T> a;
@@ -879,8 +882,8 @@ tmf_status tmf_op_autotune(tmf_op *op, const void *coeff, const void *x, void *y
 tmf_status tmf_apply_adjoint(tmf_op *op, const void *coeff, const void *x, const void *gy, void *gx, void *gk,
                              tmf_stream stream) {
   if (!op) return fail(TMF_EINVAL, "op is NULL");
-  if (op->kind != TMF_P1_DIVKGRAD && op->kind != TMF_P2_DIVKGRAD)
-    return fail(TMF_EUNSUPPORTED, "the adjoint is implemented for the div(k grad) kinds");
+  if (op->kind != TMF_P1_DIVKGRAD && op->kind != TMF_P2_DIVKGRAD && op->kind != TMF_P2V_EPSILON)
+    return fail(TMF_EUNSUPPORTED, "the adjoint is implemented for the div(k grad) and epsilon kinds");
   if (!coeff || !x || !gy || !gx) return fail(TMF_EINVAL, "coeff, x, gy and gx are required");
   const void *ins[3] = {coeff, x, gy};
   for (const void *p : ins)

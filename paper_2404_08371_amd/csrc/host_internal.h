@@ -123,9 +123,11 @@ inline SeamInst<T> seam_inst(const tmf_op *op, int cfg, int64_t yoff) {
   return a;
 }
 
+// seam points per thread of an op's seam work entries
+inline int seam_ppt(const tmf_op *op) { return op->ncomp == 1 ? kSeamPointsPerThread : 1; }
 // seam work entries (instance, macro, first point, 0) of an op
 inline void seam_work(const tmf_op *op, int cfg, int inst, std::vector<int4> &w) {
-  const int chunk = 256 * (op->ncomp == 1 ? kSeamPointsPerThread : 1);
+  const int chunk = 256 * seam_ppt(op);
   for (int64_t m = 0; m < op->mesh->nt; ++m)
     for (int p0 = 0; p0 < op->nseam[cfg]; p0 += chunk) w.push_back(make_int4(inst, static_cast<int>(m), p0, 0));
 }

@@ -377,6 +377,176 @@ __device__ inline void eps_blended_elem(const T u[3][10], const T mu[10], const 
   }
 }
 
+// Coefficient gradient of the affine epsilon form (A_T linear in the nodal
+// mu): with sigma_e = sum_a W_ae E_a as in eps_elem, gy . y = sum_e sigma_e :
+// Gam_e where Gam collects the coefficients of gy . Y(sigma), so
+// gy . y = sum_{a,e} W_ae (E_a : Gam_e) and gmu_b = sum_{a,e} W(e_b)_ae M_ae.
+// Symmetric 3x3 tensors are stored as (xx, yy, zz, xy, xz, yz); S : P counts
+// the off-diagonal entries twice.
+template <typename T>
+__device__ inline void eps_strains(const T u[3][10], CPtr<T> grad, T E[4][6]) {
+  T g[3][4][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    T sp[4][3];
+    grad_coeffs(u[c], sp);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+        g[c][a][r] = sp[a][0] * grad[3 * 1 + r] + sp[a][1] * grad[3 * 2 + r] + sp[a][2] * grad[3 * 3 + r];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    E[a][0] = g[0][a][0];
+    E[a][1] = g[1][a][1];
+    E[a][2] = g[2][a][2];
+    E[a][3] = T(0.5) * (g[0][a][1] + g[1][a][0]);
+    E[a][4] = T(0.5) * (g[0][a][2] + g[2][a][0]);
+    E[a][5] = T(0.5) * (g[1][a][2] + g[2][a][1]);
+  }
+}
+
+template <typename T>
+__device__ inline void eps_gradmu(const T u[3][10], const T gy[3][10], CPtr<T> grad, T vol, T gmu[10]) {
+  T E[4][6];
+  eps_strains(u, grad, E);
+  // sym(v w^T) of a nodal vector v of gy and a barycentric gradient w, scaled by f, added to G
+  auto addsym = [](T G[6], T f, T v0, T v1, T v2, CPtr<T> w) {
+    G[0] += f * v0 * w[0];
+    G[1] += f * v1 * w[1];
+    G[2] += f * v2 * w[2];
+    G[3] += f * T(0.5) * (v0 * w[1] + v1 * w[0]);
+    G[4] += f * T(0.5) * (v0 * w[2] + v2 * w[0]);
+    G[5] += f * T(0.5) * (v1 * w[2] + v2 * w[1]);
+  };
+  const T fv = T(2) * vol, fe = T(8) * vol;
+  T gam[4][6], vt[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    vt[q] = T(0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) gam[e][q] = T(0);
+  }
+  // vertices: gy_b . (fv (4 sigma_b - sum_e sigma_e) grad lambda_b)
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    addsym(gam[b], T(4) * fv, gy[0][b], gy[1][b], gy[2][b], grad + 3 * b);
+    addsym(vt, fv, gy[0][b], gy[1][b], gy[2][b], grad + 3 * b);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) gam[e][q] -= vt[q];
+  // edges (b, c): gy_bc . (fe (sigma_c grad lambda_b + sigma_b grad lambda_c))
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int b = kEdge[e][0], c = kEdge[e][1];
+    addsym(gam[c], fe, gy[0][4 + e], gy[1][4 + e], gy[2][4 + e], grad + 3 * b);
+    addsym(gam[b], fe, gy[0][4 + e], gy[1][4 + e], gy[2][4 + e], grad + 3 * c);
+  }
+  T M[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      M[a][e] = E[a][0] * gam[e][0] + E[a][1] * gam[e][1] + E[a][2] * gam[e][2] +
+                T(2) * (E[a][3] * gam[e][3] + E[a][4] * gam[e][4] + E[a][5] * gam[e][5]);
+#pragma unroll
+  for (int b = 0; b < 10; ++b) {
+    T kb[10], Wb[4][4];
+#pragma unroll
+    for (int w = 0; w < 10; ++w) kb[w] = w == b ? T(1) : T(0);
+    weights_p2(kb, Wb);
+    T acc = T(0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc += Wb[a][e] * M[a][e];
+    gmu[b] = acc;
+  }
+}
+
+// Coefficient gradient of the blended epsilon form: mu_q = sum_b mu_b phi_b(q)
+// enters as 2 mu_q w_q |det J| eps(u):eps(v), so
+// gmu_b = sum_q phi_b(q) 2 w_q |det J| eps(u_q) : eps(gy_q).
+template <typename T>
+__device__ inline void eps_blended_gradmu(const T u[3][10], const T gy[3][10], const T P0[3], CPtr<T> JT,
+                                          const T s[3], CPtr<T> qtab, int nq, T gmu[10]) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) gmu[i] = T(0);
+  for (int q = 0; q < nq; ++q) {
+    CPtr<T> Q = qtab + q * kQStride;  // w, bary[4], phi[10], refgrad[10][3]
+    const T xh[3] = {Q[2], Q[3], Q[4]};
+    T xi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xi[d] = P0[d] + JT[3 * d + 0] * xh[0] + JT[3 * d + 1] * xh[1] + JT[3 * d + 2] * xh[2];
+    const T rho = s[0] * xi[0] + s[1] * xi[1] + s[2] * xi[2];
+    const T n2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+    const T inv = T(1) / sqrt(n2);
+    const T a0 = rho * inv;
+    const T c3i = rho * inv * inv * inv;
+    T D[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) D[r][cc] = xi[r] * (s[cc] * inv - c3i * xi[cc]) + (r == cc ? a0 : T(0));
+    T J[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) J[r][cc] = D[r][0] * JT[0 + cc] + D[r][1] * JT[3 + cc] + D[r][2] * JT[6 + cc];
+    T Ji[3][3];
+    Ji[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    Ji[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    Ji[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    Ji[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    Ji[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    Ji[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    Ji[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    Ji[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    Ji[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const T det = J[0][0] * Ji[0][0] + J[0][1] * Ji[1][0] + J[0][2] * Ji[2][0];
+    const T idet = T(1) / det;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) Ji[r][cc] *= idet;
+    CPtr<T> RG = Q + 15;
+    // physical gradients of u and gy
+    T gu[3][3], gg[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T ru[3], rg[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        T au = T(0), ag = T(0);
+#pragma unroll
+        for (int i = 0; i < 10; ++i) {
+          au += u[c][i] * RG[3 * i + r];
+          ag += gy[c][i] * RG[3 * i + r];
+        }
+        ru[r] = au;
+        rg[r] = ag;
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        gu[c][d] = ru[0] * Ji[0][d] + ru[1] * Ji[1][d] + ru[2] * Ji[2][d];
+        gg[c][d] = rg[0] * Ji[0][d] + rg[1] * Ji[1][d] + rg[2] * Ji[2][d];
+      }
+    }
+    // eps(u) : eps(gy) = sum_{d,e} sym(gu)_de sym(gg)_de
+    T ee = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int e = 0; e < 3; ++e) ee += T(0.25) * (gu[d][e] + gu[e][d]) * (gg[d][e] + gg[e][d]);
+    const T f = T(2) * Q[0] * fabs(det) * ee;
+#pragma unroll
+    for (int i = 0; i < 10; ++i) gmu[i] += f * Q[5 + i];
+  }
+}
+
 template <typename T, int KIND, int MAP, int TX, int TY, int TZ>
 struct TileCfg {
   static constexpr int RX = 2 * TX + 1, RY = 2 * TY + 1, RZ = 2 * TZ + 1;
@@ -393,15 +563,18 @@ struct TileCfg {
   static_assert(TX == 4 || TX == 8, "row pitch chosen for TX = 4 or 8");
   static_assert(RXP >= OO + TX && (2 * RXP - TX) % 16 == 0, "row pitch");
   static constexpr int C = TX * TY * TZ;
+  static constexpr bool EPS = KIND == P2V_EPSILON || KIND == P2V_EPSILON_GRADMU;  // vector element
   static constexpr int NC = KIND == P2V_EPSILON ? 3 : 1;  // output components
   // diagonal mode: no x is staged, each micro-tet adds its local diagonal
   static constexpr bool DIAG = KIND == P2_LAPLACE_DIAG || KIND == P2_DIVKGRAD_DIAG;
-  // coefficient-gradient mode: x and gy staged (both masked), no coefficient;
+  // coefficient-gradient modes: x and gy staged (both masked), no coefficient;
   // the output gk is not zeroed on Dirichlet DoFs (boundary values of k act
   // on interior rows)
-  static constexpr bool GRADK = KIND == P2_DIVKGRAD_GRADK;
-  static constexpr int NCI = GRADK ? 2 : NC;  // staged input vectors
-  static constexpr bool HASK = KIND != P2_LAPLACE && KIND != P2_LAPLACE_DIAG && !GRADK;
+  static constexpr bool GRADK = KIND == P2_DIVKGRAD_GRADK, GRADMU = KIND == P2V_EPSILON_GRADMU;
+  static constexpr bool GRAD = GRADK || GRADMU;
+  static constexpr int NCX = GRADMU ? 3 : GRADK ? 1 : NC;   // components of x
+  static constexpr int NCI = GRAD ? 2 * NCX : NC;           // staged input vectors (x, then gy)
+  static constexpr bool HASK = KIND != P2_LAPLACE && KIND != P2_LAPLACE_DIAG && !GRAD;
   // Scalar kinds: WPG wavefronts per workgroup, wavefront w applying the
   // micro-tet types t = w (mod WPG) to every cube of the box, so the type is
   // a compile-time constant inside each loop (LDS node offsets become
@@ -414,7 +587,7 @@ struct TileCfg {
   // per CU, beat one 6-wavefront group; wavefronts then take (type, cube)
   // slots with a wave-uniform type)
   static constexpr int WPG = C == 64 ? 3 : 6;
-  static constexpr int NTH = KIND == P2V_EPSILON ? 256 : 64 * WPG;
+  static constexpr int NTH = EPS ? 256 : 64 * WPG;
   static_assert(C % 64 == 0, "every lane of a wavefront needs a cube: 64 | cubes per tile");
 };
 
@@ -450,6 +623,31 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
     for (int v = 0; v < 10; ++v)
 #pragma unroll
       for (int c = 0; c < 3; ++c) atomicAdd(&sy[c][li[v]], double(y[c][v]));
+  } else if constexpr (KIND == P2V_EPSILON_GRADMU) {
+    T u[3][10], gv[3][10], gm[10];
+#pragma unroll
+    for (int v = 0; v < 10; ++v)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        u[c][v] = sx[c][li[v]];
+        gv[c][v] = sx[3 + c][li[v]];
+      }
+    if constexpr (MAP == 0) {
+      eps_gradmu(u, gv, cptr(g->grad), *cptr(&g->vol), gm);
+    } else {
+      const __attribute__((address_space(4))) MacroGeo<T> &mg =
+          *(const __attribute__((address_space(4))) MacroGeo<T> *)(D->mgeo + m);
+      const T bc[3] = {T(bxc + kOff[t][0][0]), T(byc + kOff[t][0][1]), T(bzc + kOff[t][0][2])};
+      const T inv_n = T(1) / T(D->n);
+      T P0[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        P0[d] = mg.v0[d] + (mg.JM[3 * d + 0] * bc[0] + mg.JM[3 * d + 1] * bc[1] + mg.JM[3 * d + 2] * bc[2]) * inv_n;
+      const T sv[3] = {mg.s[0], mg.s[1], mg.s[2]};
+      eps_blended_gradmu(u, gv, P0, cptr(g->JT), sv, cptr(a.qtab), a.nq, gm);
+    }
+#pragma unroll
+    for (int v = 0; v < 10; ++v) atomicAdd(&sy[0][li[v]], double(gm[v]));
   } else if constexpr (KIND == P2_DIVKGRAD_GRADK) {
     T u[10], gv[10], gk[10];
 #pragma unroll
@@ -569,7 +767,7 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
   const T *xb[NCI];
   T *yb[NC];
 #pragma unroll
-  for (int c = 0; c < NCI; ++c) xb[c] = (Cfg::GRADK && c == 1 ? a.x2 : a.x + c * nl) + base;
+  for (int c = 0; c < NCI; ++c) xb[c] = (c < Cfg::NCX ? a.x + c * nl : a.x2 + (c - Cfg::NCX) * nl) + base;
 #pragma unroll
   for (int c = 0; c < NC; ++c) yb[c] = a.y + base + c * nl;
   const T *kb = HASK ? a.k + base : nullptr;
@@ -615,7 +813,7 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
   __syncthreads();
 
   // 2. micro-tets
-  if constexpr (KIND != P2V_EPSILON) {
+  if constexpr (!Cfg::EPS) {
     // wavefront w applies the types t = w (mod WPG) to every cube
     constexpr int WPG = Cfg::WPG;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
@@ -653,7 +851,7 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
     const bool excl = ((info >> 4) & 1) && ((rx & 1) || ((rx > 0 || bx0 == 0) && rx < 2 * TX));
     const int sl = lds_slot(rx, row, OO, RXP);
     if (excl) {
-      const bool dir = !Cfg::GRADK && ((bnd >> zp) & 1u);
+      const bool dir = !Cfg::GRAD && ((bnd >> zp) & 1u);
       const int off = srb[row] + qi;
 #pragma unroll
       for (int c = 0; c < NC; ++c) __builtin_nontemporal_store(dir ? T(0) : T(sy[c][sl]), &yb[c][off]);
@@ -716,23 +914,16 @@ __device__ __forceinline__ void seam_sum(const SeamInst<T> &a, const int *rs, in
   }
 }
 
-// seam points per thread of a seam work entry (256 threads)
-template <int NC>
-struct SeamPPT {
-  static constexpr int value = NC == 1 ? kSeamPointsPerThread : 1;
-};
-
 // Work entries: (instance, macro, first seam point, 0) reduce up to 256 PPT
-// seam points of one macro; (instance, first member, end member, 1) reduce whole
+// seam points of one macro (PPT set by how the work list was chunked); (instance, first member, end member, 1) reduce whole
 // interface groups, one thread per member (at most 256 members).  The tile-row
 // starts of the instance are staged in dynamic LDS (`rows_lds` entries; a
 // larger table is read from global memory).
-template <typename T, int NC, int TX, int TY, int TZ>
+template <typename T, int NC, int PPT, int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) void k_seam(const SeamInst<T> *__restrict__ insts, const int4 *__restrict__ work,
                                               T *__restrict__ y, const uint8_t *__restrict__ active, int flags,
                                               int rows_lds) {
   const bool local = flags & kSeamLocal;
-  constexpr int PPT = SeamPPT<NC>::value;
   extern __shared__ int srs[];
   __shared__ T sv[NC][256];
   __shared__ uint8_t sd[256];
@@ -865,6 +1056,10 @@ hipError_t launch_tile_apply(const TileArgs<T> &a, int kind, int map, int cfg, h
     case P2_LAPLACE_DIAG: return launch_kind<T, P2_LAPLACE_DIAG, 0>(a, cfg, s);
     case P2_DIVKGRAD_DIAG: return launch_kind<T, P2_DIVKGRAD_DIAG, 0>(a, cfg, s);
     case P2_DIVKGRAD_GRADK: return launch_kind<T, P2_DIVKGRAD_GRADK, 0>(a, cfg, s);
+    case P2V_EPSILON_GRADMU:
+      if (cfg != 0) return hipErrorInvalidValue;
+      return map == 0 ? launch_cfg<T, P2V_EPSILON_GRADMU, 0, 4, 4, 4>(a, s)
+                      : launch_cfg<T, P2V_EPSILON_GRADMU, 1, 4, 4, 4>(a, s);
     case P2V_EPSILON:
       // the epsilon tiles stage 3 components; only the smallest tile fits LDS twice per CU
       if (cfg != 0) return hipErrorInvalidValue;
@@ -879,28 +1074,35 @@ template hipError_t launch_tile_apply<float>(const TileArgs<float> &, int, int, 
 
 template <typename T>
 hipError_t launch_seam_gather(const SeamInst<T> *inst, const int4 *work, int nwork, T *y, const uint8_t *active,
-                              int flags, int ncomp, int cfg, int rows_lds, hipStream_t s) {
+                              int flags, int ncomp, int ppt, int cfg, int rows_lds, hipStream_t s) {
   if (nwork == 0) return hipSuccess;
   const dim3 grid(nwork);
   const size_t sh = static_cast<size_t>(rows_lds) * sizeof(int);
-  if (ncomp == 3) {
-    if (cfg != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_seam<T, 3, 4, 4, 4>), grid, dim3(256), sh, s, inst, work, y, active, flags, rows_lds);
+#define TMF_SEAM(NC_, PPT_, TX_, TY_, TZ_)                                                                   \
+  hipLaunchKernelGGL((k_seam<T, NC_, PPT_, TX_, TY_, TZ_>), grid, dim3(256), sh, s, inst, work, y, active, flags, \
+                     rows_lds)
+  if (ncomp == 3 || ppt == 1) {
+    // vector fields and the scalar gradient of a vector operator: cfg 0, one point per thread
+    if (cfg != 0 || ppt != 1) return hipErrorInvalidValue;
+    if (ncomp == 3) TMF_SEAM(3, 1, 4, 4, 4);
+    else TMF_SEAM(1, 1, 4, 4, 4);
     return hipGetLastError();
   }
+  if (ppt != kSeamPointsPerThread) return hipErrorInvalidValue;
   switch (cfg) {
-    case 0: hipLaunchKernelGGL((k_seam<T, 1, 4, 4, 4>), grid, dim3(256), sh, s, inst, work, y, active, flags, rows_lds); break;
-    case 1: hipLaunchKernelGGL((k_seam<T, 1, 8, 4, 2>), grid, dim3(256), sh, s, inst, work, y, active, flags, rows_lds); break;
-    case 2: hipLaunchKernelGGL((k_seam<T, 1, 8, 4, 4>), grid, dim3(256), sh, s, inst, work, y, active, flags, rows_lds); break;
-    case 3: hipLaunchKernelGGL((k_seam<T, 1, 4, 4, 8>), grid, dim3(256), sh, s, inst, work, y, active, flags, rows_lds); break;
+    case 0: TMF_SEAM(1, kSeamPointsPerThread, 4, 4, 4); break;
+    case 1: TMF_SEAM(1, kSeamPointsPerThread, 8, 4, 2); break;
+    case 2: TMF_SEAM(1, kSeamPointsPerThread, 8, 4, 4); break;
+    case 3: TMF_SEAM(1, kSeamPointsPerThread, 4, 4, 8); break;
     default: return hipErrorInvalidValue;
   }
+#undef TMF_SEAM
   return hipGetLastError();
 }
 
 template hipError_t launch_seam_gather<double>(const SeamInst<double> *, const int4 *, int, double *,
-                                               const uint8_t *, int, int, int, int, hipStream_t);
+                                               const uint8_t *, int, int, int, int, int, hipStream_t);
 template hipError_t launch_seam_gather<float>(const SeamInst<float> *, const int4 *, int, float *, const uint8_t *,
-                                              int, int, int, int, hipStream_t);
+                                              int, int, int, int, int, hipStream_t);
 
 }  // namespace tmf

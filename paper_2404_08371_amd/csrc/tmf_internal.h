@@ -83,8 +83,9 @@ __host__ __device__ inline int zero_pattern(int i, int j, int k, int N) {
 
 enum Kind { P1_LAPLACE = 0, P1_DIVKGRAD = 1, P2_LAPLACE = 2, P2_DIVKGRAD = 3, P2V_EPSILON = 4 };
 // element-kernel modes besides the applies: diag(A) of a scalar P2 kind, and
-// the coefficient gradient gk_b = gy . (dA/dk_b) x of P2 div(k grad)
-enum KernelMode { P2_LAPLACE_DIAG = 5, P2_DIVKGRAD_DIAG = 6, P2_DIVKGRAD_GRADK = 7 };
+// the coefficient gradients gk_b = gy . (dA/dk_b) x of P2 div(k grad) and of
+// the epsilon operator (k = mu)
+enum KernelMode { P2_LAPLACE_DIAG = 5, P2_DIVKGRAD_DIAG = 6, P2_DIVKGRAD_GRADK = 7, P2V_EPSILON_GRADMU = 8 };
 
 template <typename T>
 struct LatticeArgs {
@@ -200,8 +201,10 @@ hipError_t launch_tile_apply(const TileArgs<T> &a, int kind, int map, int tile_c
 // sums instead of 0)
 constexpr int kSeamLocal = 1, kSeamKeepBoundary = 2;
 template <typename T>
+// ncomp: components of y; ppt: seam points per thread, as the work list was
+// chunked (256 ppt points per seam entry)
 hipError_t launch_seam_gather(const SeamInst<T> *inst, const int4 *work, int nwork, T *y, const uint8_t *active,
-                              int flags, int ncomp, int tile_cfg, int rows_lds, hipStream_t s);
+                              int flags, int ncomp, int ppt, int tile_cfg, int rows_lds, hipStream_t s);
 template <typename T>
 hipError_t launch_interface_sum(const GroupArgs &g, T *y, hipStream_t s);
 template <typename T>

@@ -157,14 +157,16 @@ class Operator:
         return v
 
     def adjoint(self, coeff, x, gy, gx=None, gk=None, want_gk=True):
-        """Reverse mode of the macro-local apply of the div(k grad) kinds (P1, P2): returns (gx, gk)."""
-        pk, px, pg = self._vec(coeff, "coeff", 1), self._vec(x, "x", 1), self._vec(gy, "gy", 1)
+        """Reverse mode of the macro-local apply of the div(k grad) kinds (P1, P2) and the epsilon
+        operator: returns (gx, gk); gk is the gradient for the coefficient (k or mu)."""
+        nc = self.ncomp
+        pk, px, pg = self._vec(coeff, "coeff", 1), self._vec(x, "x", nc), self._vec(gy, "gy", nc)
         if gx is None:
             gx = torch.empty_like(x)
         if gk is None and want_gk:
             gk = torch.empty_like(coeff)
         with torch.cuda.device(x.device):
-            check(lib().tmf_apply_adjoint(self._h, pk, px, pg, self._vec(gx, "gx", 1),
+            check(lib().tmf_apply_adjoint(self._h, pk, px, pg, self._vec(gx, "gx", nc),
                                           self._vec(gk, "gk", 1) if gk is not None else None,
                                           _stream_handle(x.device)))
         return gx, gk

@@ -1,4 +1,8 @@
-"""GPU reverse mode of the div(k grad) operators (hand-written adjoint kernels).
+"""GPU reverse mode of the div(k grad) and epsilon operators (hand-written adjoint kernels).
+
+Epsilon (at the end): dL/dx and dL/dmu on the affine shell (level 2) and the
+radially blended shell (level 1, 14-point rule) against the oracle, FP64
+1e-12; FP32 against FP64.
 
 P2 div(k grad) (the same checks, below the P1 ones): reference tet at level 5
 and the 6-macro Kuhn cube at level 3 against the oracle's gradients; 16
@@ -222,3 +226,58 @@ def test_p2_coefficient_gradient_is_the_linear_part():
     lin = (w * (op.apply(x, k.detach() + dk) - op.apply(x, k.detach()))).sum().item()
     assert abs((k.grad * dk).sum().item() - lin) <= 1e-11 * max(abs(lin), 1.0)
 
+
+
+# ------------------------------------------------------------- epsilon
+def eps_problem(mesh, level, prec=T.F64):
+    from helpers import MESHES, inputs
+    mk, mp = MESHES[mesh]
+    v, t = mk()
+    m = T.Mesh(v, t, level, mp)
+    rule = W.quadrature.rule_degree5() if mp == 1 else None
+    op = T.Operator(m, T.P2V_EPSILON, prec, T.BC_DIRICHLET_ZERO, rule=rule)
+    info = m.dof_info(2)
+    x, mu = inputs(O.P2V_EPSILON, info["keys"], info["xyz"], 6)
+    b = np.concatenate([W.uniform_from_keys(7, info["keys"], stream=c) for c in range(3)])
+    return m, op, info, mu, x, b
+
+
+@pytest.mark.parametrize("mesh,level", [("flatshell", 2), ("shell", 1)])
+def test_eps_gradients_match_oracle(mesh, level):
+    """Affine and radially blended epsilon operator: dL/dx and dL/dmu against the oracle (FP64, 1e-12)."""
+    from helpers import inputs, oracle_problem
+    print("eps adjoint case", mesh, level, flush=True)
+    m, op, info, mu, x, b = eps_problem(mesh, level)
+    mut = torch.tensor(mu, device="cuda", requires_grad=True)
+    xt = torch.tensor(x, device="cuda", requires_grad=True)
+    own = torch.tensor(np.tile(info["owner"], 3), device="cuda", dtype=torch.float64)
+    y = TmfApply.apply(xt, mut, op)
+    L = 0.5 * (((y - torch.tensor(b, device="cuda")) ** 2) * own).sum()
+    L.backward()
+    pr = oracle_problem(mesh, level, O.P2V_EPSILON, O.BC_DIRICHLET_ZERO)
+    xo, muo = inputs(O.P2V_EPSILON, pr.keys, pr.xyz, 6)
+    bo = np.concatenate([W.uniform_from_keys(7, pr.keys, stream=c) for c in range(3)])
+    Lo, gxo, gmo = pr.loss_gradients(muo, xo, bo)
+    assert abs(L.item() - Lo) <= 1e-12 * abs(Lo)
+    gx, gm = xt.grad.cpu().numpy(), mut.grad.cpu().numpy()
+    tx = np.zeros(3 * pr.n_unique)
+    for c in range(3):
+        np.add.at(tx, c * pr.n_unique + pr.uid, gx[c * pr.n_local:(c + 1) * pr.n_local])
+    assert np.linalg.norm(tx - pr.to_unique(gxo)) <= 1e-12 * np.linalg.norm(gxo)
+    tm = np.zeros(pr.n_unique)
+    np.add.at(tm, pr.uid, gm)
+    gmu = np.zeros(pr.n_unique)
+    gmu[pr.uid] = gmo
+    assert np.linalg.norm(tm - gmu) <= 1e-12 * np.linalg.norm(gmu)
+
+
+def test_eps_adjoint_fp32_matches_fp64():
+    m, op, info, mu, x, b = eps_problem("shell", 2)
+    op32 = T.Operator(m, T.P2V_EPSILON, T.F32, T.BC_DIRICHLET_ZERO, rule=W.quadrature.rule_degree5())
+    gy = torch.tensor(b, device="cuda")
+    gx64, gm64 = op.adjoint(torch.tensor(mu, device="cuda"), torch.tensor(x, device="cuda"), gy)
+    gx32, gm32 = op32.adjoint(torch.tensor(mu, device="cuda", dtype=torch.float32),
+                              torch.tensor(x, device="cuda", dtype=torch.float32), gy.float())
+    for a64, a32 in ((gx64, gx32), (gm64, gm32)):
+        a64, a32 = a64.cpu().numpy(), a32.double().cpu().numpy()
+        assert np.abs(a64 - a32).max() <= 2e-5 * np.abs(a64).max()
