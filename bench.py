@@ -14,7 +14,8 @@ Also reported under "forms": the other operators and precisions on their
 workloads (P1 Laplacian at levels 4 and 9, the P1 div(k grad) forward and
 fused adjoint at levels 7 and 9, the P2 FP32 apply, the P2 FP64 apply at
 level 7, the P2 div(k grad) adjoint on the headline workload, the vector
-epsilon operator on the radially blended shell in FP64 and FP32) and the
+epsilon operator on the radially blended shell in FP64 and FP32 and its
+FP64 adjoint) and the
 batched FP32-in-FP64 refinement solve (Jacobi-preconditioned and plain).
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
@@ -48,6 +49,8 @@ FLOPS = {
                                # gradient coefficients 40, h 72, Gam 44, M 112, 10 x 16-term contractions 320)
     "eps_affine": 970,         # per micro-tet
     "eps_blended_per_q": 657,  # per micro-tet and quadrature point (map Jacobian, inverse, 2 x 90-term contractions)
+    "eps_blended_adjoint_per_q": 1337,  # forward of gy (657) + mu gradient (680: map Jacobian and inverse,
+                                        # gradients of x and gy, strain contraction, 10-node scatter)
 }
 
 
@@ -403,6 +406,11 @@ def main():
             oe = T.Operator(ms6, T.P2V_EPSILON, prec, T.BC_DIRICHLET_ZERO, rule=rule)
             form("eps_blended_%s_shell_l6" % nm, ms6, oe, "eps", 4,
                  n_elements(24, 6) * 14 * FLOPS["eps_blended_per_q"], 7 * bpd * oe.n_local, pk, 5)
+            if prec == T.F64:
+                # adjoint: gx = L(mu) gy and the mu gradient (gy, mu -> gx; x, gy -> gmu)
+                form("eps_blended_adjoint_fp64_shell_l6", ms6, oe, "eps", 4,
+                     n_elements(24, 6) * 14 * FLOPS["eps_blended_adjoint_per_q"], 14 * bpd * oe.n_local, pk, 5,
+                     adjoint=True)
             del oe
         # batched mixed-precision solve: 32 reference-tet instances, levels in {3..7}
         log("batched FP32-in-FP64 refinement, 32 instances")
