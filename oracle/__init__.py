@@ -8,5 +8,5 @@ Modules: lattice (refinement, layout, keys), elements (element matrices from
 their definitions), apply (matrix-free y = A x, sparse assembly, gradients,
 conjugate gradients).
 """
-from .apply import (Problem, P1_LAPLACE, P1_DIVKGRAD, P2_LAPLACE, P2_DIVKGRAD, P2V_EPSILON,  # noqa: F401
+from .apply import (Problem, P1_LAPLACE, P1_DIVKGRAD, P2_LAPLACE, P2_DIVKGRAD, P2V_EPSILON, N1_CURLCURL,  # noqa: F401
                     BC_NONE, BC_DIRICHLET_ZERO, MAP_AFFINE, MAP_SHELL_RADIAL)

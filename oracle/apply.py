@@ -29,13 +29,20 @@ from . import elements as el
 from .lattice import (EDGES, TYPE_NAMES, barycentric, lattice_points, lattice_size,
                       micro_tets, packed_index, point_keys)
 
-P1_LAPLACE, P1_DIVKGRAD, P2_LAPLACE, P2_DIVKGRAD, P2V_EPSILON = range(5)
+P1_LAPLACE, P1_DIVKGRAD, P2_LAPLACE, P2_DIVKGRAD, P2V_EPSILON, N1_CURLCURL = range(6)
 BC_NONE, BC_DIRICHLET_ZERO = 0, 1
 MAP_AFFINE, MAP_SHELL_RADIAL = 0, 1
 
-SPACE = {P1_LAPLACE: 1, P1_DIVKGRAD: 1, P2_LAPLACE: 2, P2_DIVKGRAD: 2, P2V_EPSILON: 2}
+# N1 (curl-curl + mass) uses the P2 lattice: an edge DoF sits at the edge's
+# midpoint slot (vertex slots carry no DoF: their rows and columns are zero),
+# and the coefficients alpha, beta sit at the vertex slots of a
+# two-component coefficient vector [alpha | beta].  The DoF is the tangential
+# integral along the edge oriented from the endpoint with the smaller
+# canonical key to the larger.
+SPACE = {P1_LAPLACE: 1, P1_DIVKGRAD: 1, P2_LAPLACE: 2, P2_DIVKGRAD: 2, P2V_EPSILON: 2, N1_CURLCURL: 2}
 HAS_COEFF = {P1_LAPLACE: False, P1_DIVKGRAD: True, P2_LAPLACE: False, P2_DIVKGRAD: True,
-             P2V_EPSILON: True}
+             P2V_EPSILON: True, N1_CURLCURL: True}
+COEFF_COMP = {N1_CURLCURL: 2}
 
 CHUNK = 65536
 
@@ -116,10 +123,28 @@ class Problem:
                         nodes = packed_index(np.concatenate([vn, en], 1), self.N)
                     yield m, tn, P, nodes + m * self.L
 
-    def element_matrices(self, P, c_e, macro):
+    def _coeff_e(self, coeff, nodes):
+        """Element coefficient values (N1: alpha and beta at the 4 vertex slots)."""
+        if not HAS_COEFF[self.kind]:
+            return None
+        if self.kind == N1_CURLCURL:
+            v = nodes[:, :4]
+            return coeff[v], coeff[self.n_local + v]
+        return coeff[nodes]
+
+    def element_matrices(self, P, c_e, macro, nodes=None):
         k = self.kind
         if self.map == MAP_SHELL_RADIAL and k != P2V_EPSILON:
             raise ValueError("the blended map is defined for the epsilon operator")
+        if k == N1_CURLCURL:
+            # local orientation a -> b (a < b) turned to the global one: the
+            # edge DoF's sign is + when the canonical keys increase from a to b
+            A6 = el.n1_curlcurl_mass(P, *c_e)
+            u = self.uid[nodes[:, :4]]
+            sgn = np.stack([np.where(u[:, a] < u[:, b], 1.0, -1.0) for a, b in EDGES], 1)
+            A = np.zeros((len(P), 10, 10))
+            A[:, 4:, 4:] = sgn[:, :, None] * A6 * sgn[:, None, :]
+            return A
         if k == P1_LAPLACE:
             return el.p1_laplace(P)
         if k == P1_DIVKGRAD:
@@ -146,7 +171,7 @@ class Problem:
             raise ValueError("x has shape %s, expected (%d,)" % (x.shape, self.ncomp * self.n_local))
         if HAS_COEFF[self.kind]:
             coeff = np.asarray(coeff, dtype=np.float64)
-            if coeff.shape != (self.n_local,):
+            if coeff.shape != (COEFF_COMP.get(self.kind, 1) * self.n_local,):
                 raise ValueError("coefficient has the wrong shape")
         return x, coeff
 
@@ -179,8 +204,7 @@ class Problem:
                 if not sel.any():
                     continue
                 P, nodes = P[sel], nodes[sel]
-            c_e = coeff[nodes] if HAS_COEFF[self.kind] else None
-            A = self.element_matrices(P, c_e, m)
+            A = self.element_matrices(P, self._coeff_e(coeff, nodes), m, nodes)
             idx = self._dof_index(nodes)
             ye = np.einsum("eji,ei->ej", A, xm[idx])
             y += np.bincount(idx.ravel(), weights=ye.ravel(), minlength=y.size)
@@ -194,8 +218,7 @@ class Problem:
             coeff = np.asarray(coeff, dtype=np.float64)
         d = np.zeros(self.ncomp * self.n_local)
         for m, tn, P, nodes in self.element_batches():
-            c_e = coeff[nodes] if HAS_COEFF[self.kind] else None
-            A = self.element_matrices(P, c_e, m)
+            A = self.element_matrices(P, self._coeff_e(coeff, nodes), m, nodes)
             idx = self._dof_index(nodes)
             de = np.einsum("ejj->ej", A)
             d += np.bincount(idx.ravel(), weights=de.ravel(), minlength=d.size)
@@ -208,8 +231,7 @@ class Problem:
         if HAS_COEFF[self.kind]:
             coeff = np.asarray(coeff, dtype=np.float64)
         for m, tn, P, nodes in self.element_batches():
-            c_e = coeff[nodes] if HAS_COEFF[self.kind] else None
-            A = self.element_matrices(P, c_e, m)
+            A = self.element_matrices(P, self._coeff_e(coeff, nodes), m, nodes)
             u = self.uid[nodes]
             if self.ncomp == 3:
                 u = np.concatenate([u + c * self.n_unique for c in range(3)], 1)

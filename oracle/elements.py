@@ -13,6 +13,9 @@ function j, column = trial function i) for
 * P2k : k grad(phi_i).grad(phi_j), k nodal P2             (equation P2V)
 * EPS : 2 mu eps(u):eps(v), eps = sym grad, vector P2, mu nodal P2
         (the symmetric-gradient operator; not in the paper, textbook definition)
+* N1  : alpha curl(phi_i).curl(phi_j) + beta phi_i.phi_j, first-kind
+        lowest-order Nedelec elements, alpha and beta nodal P1 (equation N1 of
+        section "Curl-Curl and Mass")
 
 All signs are those of positive semi-definite stiffness matrices, as the
 paper's local-matrix equations define them.
@@ -191,6 +194,42 @@ def eps_affine(P, mu):
     A = np.einsum("...ijab,...acbd->...djci", Mmu, S)  # rows (d,j), cols (c,i)
     sh = A.shape[:-4]
     return A.reshape(sh + (30, 30))
+
+
+def _lambda3():
+    """I3[m,p,q] = (1/|T|) int lambda_m lambda_p lambda_q (exact)."""
+    I3 = np.zeros((4, 4, 4))
+    for m in range(4):
+        for p in range(4):
+            for q in range(4):
+                I3[m, p, q] = float(bary_integral(_mul(_mul(_lam(m), _lam(p)), _lam(q))))
+    return I3
+
+
+N1_I3 = _lambda3()
+
+
+def n1_curlcurl_mass(P, alpha, beta):
+    """Nedelec (first kind, lowest order) element matrix of
+    int alpha curl(phi_i).curl(phi_j) + beta phi_i.phi_j, edges i = (a, b) in
+    the order 01,02,03,12,13,23, each oriented from a to b:
+        phi_ab = lambda_a grad(lambda_b) - lambda_b grad(lambda_a),
+        curl phi_ab = 2 grad(lambda_a) x grad(lambda_b),
+    alpha, beta nodal P1 (...,4).  alpha enters the constant curl product
+    through its mean; beta phi_i.phi_j is a cubic in the barycentrics."""
+    vol, g = geometry(P)
+    alpha, beta = np.asarray(alpha, float), np.asarray(beta, float)
+    G = np.einsum("...ad,...bd->...ab", g, g)
+    curls = np.stack([2.0 * np.cross(g[..., a, :], g[..., b, :]) for a, b in EDGES], -2)  # (...,6,3)
+    K = alpha.mean(-1)[..., None, None] * np.einsum("...id,...jd->...ij", curls, curls)
+    # B3[p,q] = (1/|T|) int beta lambda_p lambda_q
+    B3 = np.einsum("...m,mpq->...pq", beta, N1_I3)
+    M = np.empty(K.shape)
+    for i, (a, b) in enumerate(EDGES):
+        for j, (c, d) in enumerate(EDGES):
+            M[..., i, j] = (B3[..., a, c] * G[..., b, d] - B3[..., a, d] * G[..., b, c]
+                            - B3[..., b, c] * G[..., a, d] + B3[..., b, d] * G[..., a, c])
+    return vol[..., None, None] * (K + M)
 
 
 # ------------------------------------------------- reference-element evaluation
