@@ -18,6 +18,17 @@
  *   TMF_P2_DIVKGRAD  int k grad(phi_i).grad(phi_j), k nodal quadratic (equation P2V)
  *   TMF_P2V_EPSILON  int 2 mu eps(u):eps(v), eps = sym grad, vector quadratic
  *                    Lagrange, mu nodal quadratic
+ *   TMF_N1_CURLCURL  int alpha curl(phi_i).curl(phi_j) + beta phi_i.phi_j,
+ *                    first-kind lowest-order Nedelec elements, alpha and beta
+ *                    nodal linear (equation N1, section "Curl-Curl and Mass")
+ *
+ * N1 layout: the operator uses the quadratic lattice (N = 2n).  The DoF of a
+ * micro-edge sits at the slot of its midpoint and is the tangential integral
+ * along the edge oriented from the endpoint with the smaller canonical key
+ * (the ordering of tmf_mesh_dof_info's keys, compared as 8 signed integers
+ * in turn) to the larger; vertex slots carry no DoF (zero rows, their inputs
+ * ignored).  Its coefficient vector holds 2 * n_local values: alpha, then
+ * beta, each read at the vertex slots only.
  *
  * All are positive semi-definite stiffness matrices.  The affine forms are
  * integrated exactly (the integrand of P2V has degree 4; the kernels use the
@@ -85,6 +96,7 @@ typedef int tmf_status;
 #define TMF_P2_LAPLACE 2
 #define TMF_P2_DIVKGRAD 3
 #define TMF_P2V_EPSILON 4
+#define TMF_N1_CURLCURL 5
 
 #define TMF_F64 0
 #define TMF_F32 1
@@ -144,7 +156,7 @@ tmf_status tmf_mesh_dof_info(const tmf_mesh *mesh, int space, int64_t *keys, dou
                              uint8_t *owner, uint8_t *boundary);
 
 /* Create an operator on `mesh` (the mesh must outlive the operator).
- *   kind   TMF_P1_LAPLACE .. TMF_P2V_EPSILON
+ *   kind   TMF_P1_LAPLACE .. TMF_N1_CURLCURL
  *   prec   TMF_F64 or TMF_F32: element type of coefficient, x and y; the
  *          geometry constants are computed in FP64 on the host and rounded
  *          once for TMF_F32

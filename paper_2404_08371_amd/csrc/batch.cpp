@@ -133,7 +133,8 @@ tmf_status tmf_batch_create(tmf_op *const *ops, int count, tmf_batch **out) {
   for (int i = 0; i < count; ++i) {
     const tmf_op *o = ops[i];
     if (!o) return fail(TMF_EINVAL, "operator %d is NULL", i);
-    if (o->space != 2) return fail(TMF_EUNSUPPORTED, "batches hold P2 / epsilon operators (element kernels)");
+    if (o->space != 2 || o->kind == TMF_N1_CURLCURL)
+      return fail(TMF_EUNSUPPORTED, "batches hold P2 / epsilon operators (element kernels)");
     if (o->kind != o0->kind || o->prec != o0->prec)
       return fail(TMF_EINVAL, "operator %d differs in kind or precision from operator 0", i);
     if (o->mesh->map != TMF_MAP_AFFINE) return fail(TMF_EUNSUPPORTED, "batches hold affine meshes");

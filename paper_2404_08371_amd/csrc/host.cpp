@@ -405,7 +405,7 @@ tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const
   if (!out) return fail(TMF_EINVAL, "out is NULL");
   *out = nullptr;
   if (!mesh) return fail(TMF_EINVAL, "mesh is NULL");
-  if (kind < TMF_P1_LAPLACE || kind > TMF_P2V_EPSILON) return fail(TMF_EINVAL, "bad operator kind %d", kind);
+  if (kind < TMF_P1_LAPLACE || kind > TMF_N1_CURLCURL) return fail(TMF_EINVAL, "bad operator kind %d", kind);
   if (prec != TMF_F64 && prec != TMF_F32) return fail(TMF_EINVAL, "bad precision %d", prec);
   if (bc != TMF_BC_NONE && bc != TMF_BC_DIRICHLET_ZERO) return fail(TMF_EINVAL, "bad boundary condition %d", bc);
   const int space = kind <= TMF_P1_DIVKGRAD ? 1 : 2;
@@ -500,6 +500,30 @@ tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const
     }
     op->nchunks = static_cast<int>(ch.size());
     st = op->chunks.upload(ch.data(), ch.size());
+  }
+  if (st == TMF_OK && kind == TMF_N1_CURLCURL) {
+    // orientation of each edge slot: the lattice direction D of a midpoint
+    // m (the micro-edge direction whose odd coordinates are those of m, first
+    // nonzero component positive) runs from (m - D) / 2 to (m + D) / 2; the
+    // DoF's global orientation follows the canonical keys of the endpoints
+    static const int kDir[8][3] = {{0, 0, 0},  {1, 0, 0},  {0, 1, 0},  {1, -1, 0},
+                                   {0, 0, 1},  {1, 0, -1}, {0, 1, -1}, {1, -1, 1}};
+    const int N = S.N;
+    std::vector<int8_t> sg(static_cast<size_t>(S.n_local), 0);
+    for (int64_t mac = 0; mac < mesh->nt; ++mac) {
+      const int64_t *g = &mesh->T[4 * mac];
+      for (int k = 0; k <= N; ++k)
+        for (int j = 0; j <= N - k; ++j)
+          for (int i = 0; i <= N - k - j; ++i) {
+            const int odd = (i & 1) | ((j & 1) << 1) | ((k & 1) << 2);
+            if (odd == 0) continue;
+            const int *D = kDir[odd];
+            const Key kp = point_key(g, i - D[0], j - D[1], k - D[2], N);
+            const Key kq = point_key(g, i + D[0], j + D[1], k + D[2], N);
+            sg[static_cast<size_t>(mac * S.L + row_base(j, k, N) + i)] = kp < kq ? 1 : -1;
+          }
+    }
+    st = op->sign.upload(sg.data(), sg.size());
   }
   if (st == TMF_OK && space == 2) {
     const int n = mesh->n, N = S.N;

@@ -96,6 +96,7 @@ struct tmf_op {
   DevBuf<uint32_t> shared;                // per macro: zero patterns with copies in other macros
   DevBuf<int64_t> gpos;                   // per interface-group member: macro << 32 | packed lattice point
   DevBuf<int> gpl;                        // per interface-group member: position << 16 | group size
+  DevBuf<int8_t> sign;                    // N1: per slot, global / lattice orientation of its edge (0: vertex)
   int seamrows[kNumTileCfg] = {0};        // tile-row table entries per macro, per tile shape
 };
 
@@ -158,6 +159,7 @@ InstDesc<T> make_desc(const tmf_op *op, int64_t off) {
   d.off = off;
   d.n_local = op->n_local;
   d.bnd = op->bnd.p;
+  d.sign = op->sign.p;
   d.partial = reinterpret_cast<T *>(op->partial.p);
   d.geo = reinterpret_cast<const TypeGeo<T> *>(op->geo.p);
   d.mgeo = reinterpret_cast<const MacroGeo<T> *>(op->mgeo.p);
@@ -167,6 +169,6 @@ InstDesc<T> make_desc(const tmf_op *op, int64_t off) {
 
 namespace tmf {
 inline bool has_coeff(int kind) {
-  return kind == TMF_P1_DIVKGRAD || kind == TMF_P2_DIVKGRAD || kind == TMF_P2V_EPSILON;
+  return kind == TMF_P1_DIVKGRAD || kind == TMF_P2_DIVKGRAD || kind == TMF_P2V_EPSILON || kind == TMF_N1_CURLCURL;
 }
 }  // namespace tmf

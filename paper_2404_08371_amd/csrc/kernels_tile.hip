@@ -547,6 +547,72 @@ __device__ inline void eps_blended_gradmu(const T u[3][10], const T gy[3][10], c
   }
 }
 
+// N1 curl-curl + mass on one affine tet (equation N1), lowest-order
+// first-kind Nedelec basis phi_ab = lambda_a g_b - lambda_b g_a (g = grad
+// lambda, edges a < b oriented a -> b), alpha and beta nodal P1:
+//   curl u = C = sum_e u_e c_e, c_e = 2 g_a x g_b (constant), so the curl
+//   part is y_e = |T| mean(alpha) c_e . C;
+//   u = sum_p lambda_p U_p with U_a += u_e g_b, U_b -= u_e g_a, and with
+//   B_pq = int beta lambda_p lambda_q = |T| (sum beta + beta_p + beta_q) / 120
+//   (p != q), |T| (sum beta + 2 beta_p) / 60 (p = q), V_q = sum_p B_pq U_p,
+//   the mass part is y_ab = g_b . V_a - g_a . V_b.
+template <typename T>
+__device__ inline void n1_elem(const T u[6], const T al[4], const T be[4], CPtr<T> g, T vol, T y[6]) {
+  T c[6][3], C[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int a = kEdge[e][0], b = kEdge[e][1];
+    c[e][0] = T(2) * (g[3 * a + 1] * g[3 * b + 2] - g[3 * a + 2] * g[3 * b + 1]);
+    c[e][1] = T(2) * (g[3 * a + 2] * g[3 * b + 0] - g[3 * a + 0] * g[3 * b + 2]);
+    c[e][2] = T(2) * (g[3 * a + 0] * g[3 * b + 1] - g[3 * a + 1] * g[3 * b + 0]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) C[d] += u[e] * c[e][d];
+  }
+  const T am = T(0.25) * (al[0] + al[1] + al[2] + al[3]) * vol;
+#pragma unroll
+  for (int e = 0; e < 6; ++e) y[e] = am * (c[e][0] * C[0] + c[e][1] * C[1] + c[e][2] * C[2]);
+  T U[4][3];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) U[p][d] = T(0);
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int a = kEdge[e][0], b = kEdge[e][1];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      U[a][d] += u[e] * g[3 * b + d];
+      U[b][d] -= u[e] * g[3 * a + d];
+    }
+  }
+  const T sb = be[0] + be[1] + be[2] + be[3];
+  T B[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      B[p][q] = p == q ? vol * (sb + T(2) * be[p]) * T(1.0 / 60.0) : vol * (sb + be[p] + be[q]) * T(1.0 / 120.0);
+  T V[4][3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) V[q][d] = B[0][q] * U[0][d] + B[1][q] * U[1][d] + B[2][q] * U[2][d] + B[3][q] * U[3][d];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int a = kEdge[e][0], b = kEdge[e][1];
+    y[e] += g[3 * b + 0] * V[a][0] + g[3 * b + 1] * V[a][1] + g[3 * b + 2] * V[a][2] -
+            (g[3 * a + 0] * V[b][0] + g[3 * a + 1] * V[b][1] + g[3 * a + 2] * V[b][2]);
+  }
+}
+
+// +1 if local edge e (a -> b) of type t runs along its lattice direction (the
+// micro-edge direction with first nonzero component positive), else -1
+constexpr int n1_edge_sign(int t, int e) {
+  int d[3] = {0, 0, 0};
+  for (int c = 0; c < 3; ++c) d[c] = kOff[t][kEdge[e][1]][c] - kOff[t][kEdge[e][0]][c];
+  return d[0] != 0 ? (d[0] > 0 ? 1 : -1) : d[1] != 0 ? (d[1] > 0 ? 1 : -1) : (d[2] > 0 ? 1 : -1);
+}
+
 template <typename T, int KIND, int MAP, int TX, int TY, int TZ>
 struct TileCfg {
   static constexpr int RX = 2 * TX + 1, RY = 2 * TY + 1, RZ = 2 * TZ + 1;
@@ -575,6 +641,10 @@ struct TileCfg {
   static constexpr int NCX = GRADMU ? 3 : GRADK ? 1 : NC;   // components of x
   static constexpr int NCI = GRAD ? 2 * NCX : NC;           // staged input vectors (x, then gy)
   static constexpr bool HASK = KIND != P2_LAPLACE && KIND != P2_LAPLACE_DIAG && !GRAD;
+  // N1: edge DoFs with a per-slot orientation sign; two coefficients (alpha,
+  // beta) read at the vertex points
+  static constexpr bool N1 = KIND == N1_CURLCURL;
+  static constexpr int NK = N1 ? 2 : 1;
   // Scalar kinds: WPG wavefronts per workgroup, wavefront w applying the
   // micro-tet types t = w (mod WPG) to every cube of the box, so the type is
   // a compile-time constant inside each loop (LDS node offsets become
@@ -623,6 +693,18 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
     for (int v = 0; v < 10; ++v)
 #pragma unroll
       for (int c = 0; c < 3; ++c) atomicAdd(&sy[c][li[v]], double(y[c][v]));
+  } else if constexpr (KIND == N1_CURLCURL) {
+    T u[6], al[4], be[4], y6[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) u[e] = T(n1_edge_sign(t, e)) * sx[0][li[4 + e]];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      al[v] = sk[li[v]];
+      be[v] = sk[R + li[v]];
+    }
+    n1_elem(u, al, be, cptr(g->grad), *cptr(&g->vol), y6);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) atomicAdd(&sy[0][li[4 + e]], double(T(n1_edge_sign(t, e)) * y6[e]));
   } else if constexpr (KIND == P2V_EPSILON_GRADMU) {
     T u[3][10], gv[3][10], gm[10];
 #pragma unroll
@@ -732,7 +814,8 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
   // LDS atomics run at full speed on gfx950 where FP32 ones stall the LDS
   // pipeline, and the partial sums of a point keep 53-bit mantissas
   __shared__ double sy[NC][RP];
-  __shared__ T sk[HASK ? RP : 1];
+  __shared__ T sk[HASK ? Cfg::NK * RP : 1];
+  __shared__ int8_t ssg[Cfg::N1 ? RP : 1];  // N1: orientation sign of each box point
 
   const int tid = threadIdx.x;
   const int nxcd = 8;
@@ -775,12 +858,15 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
   // 1. stage the box: x with Dirichlet DoFs zeroed, and the coefficient.  The
   // loop is unrolled over a thread's points so that all its loads are in
   // flight together (one memory latency per tile instead of one per point).
-  constexpr int PF = (R + NTH - 1) / NTH;
-  T xv[PF][NCI], kv[PF];
+  constexpr int PF = (R + NTH - 1) / NTH, NK = Cfg::NK;
+  T xv[PF][NCI], kv[PF][NK];
+  int sgv[PF];
 #pragma unroll
   for (int p = 0; p < PF; ++p) {
     const int r = tid + p * NTH;
-    kv[p] = T(0);
+    sgv[p] = 0;
+#pragma unroll
+    for (int c = 0; c < NK; ++c) kv[p][c] = T(0);
 #pragma unroll
     for (int c = 0; c < NCI; ++c) xv[p][c] = T(0);
     if (r < R) {
@@ -793,7 +879,18 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
 #pragma unroll
           for (int c = 0; c < NCI; ++c) xv[p][c] = xb[c][off];
         }
-        if (HASK) kv[p] = kb[off];
+        if constexpr (Cfg::N1) {
+          // x in the lattice orientation; alpha and beta live at the vertex points
+          sgv[p] = D->sign[base + off];
+          xv[p][0] *= T(sgv[p]);
+          const int ry = row % RY, rz = row / RY;
+          if (!(rx & 1) && !(ry & 1) && !(rz & 1)) {
+            kv[p][0] = kb[off];
+            kv[p][1] = kb[nl + off];
+          }
+        } else if (HASK) {
+          kv[p][0] = kb[off];
+        }
       }
     }
   }
@@ -807,7 +904,11 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
       for (int c = 0; c < NCI; ++c) sx[c][sl] = xv[p][c];
 #pragma unroll
       for (int c = 0; c < NC; ++c) sy[c][sl] = 0.0;
-      if (HASK) sk[sl] = kv[p];
+      if (HASK) {
+#pragma unroll
+        for (int c = 0; c < NK; ++c) sk[c * RP + sl] = kv[p][c];
+      }
+      if constexpr (Cfg::N1) ssg[sl] = static_cast<int8_t>(sgv[p]);
     }
   }
   __syncthreads();
@@ -850,16 +951,19 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
     const int zp = (qi == lim) | ((qi == 0) << 1) | (info & 12);
     const bool excl = ((info >> 4) & 1) && ((rx & 1) || ((rx > 0 || bx0 == 0) && rx < 2 * TX));
     const int sl = lds_slot(rx, row, OO, RXP);
+    // N1: back to the global orientation (partials too, so that the gather
+    // adds values of one orientation)
+    const T osg = Cfg::N1 ? T(ssg[sl]) : T(1);
     if (excl) {
       const bool dir = !Cfg::GRAD && ((bnd >> zp) & 1u);
       const int off = srb[row] + qi;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) __builtin_nontemporal_store(dir ? T(0) : T(sy[c][sl]), &yb[c][off]);
+      for (int c = 0; c < NC; ++c) __builtin_nontemporal_store(dir ? T(0) : osg * T(sy[c][sl]), &yb[c][off]);
     } else {
-#pragma unroll
       // plain stores: the gather kernel reads these next (measured faster
       // than non-temporal ones, and than a compact surface-only layout)
-      for (int c = 0; c < NC; ++c) pt[c * R + r] = T(sy[c][sl]);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) pt[c * R + r] = osg * T(sy[c][sl]);
     }
   }
 }
@@ -1053,6 +1157,7 @@ hipError_t launch_tile_apply(const TileArgs<T> &a, int kind, int map, int cfg, h
   switch (kind) {
     case P2_LAPLACE: return launch_kind<T, P2_LAPLACE, 0>(a, cfg, s);
     case P2_DIVKGRAD: return launch_kind<T, P2_DIVKGRAD, 0>(a, cfg, s);
+    case N1_CURLCURL: return launch_kind<T, N1_CURLCURL, 0>(a, cfg, s);
     case P2_LAPLACE_DIAG: return launch_kind<T, P2_LAPLACE_DIAG, 0>(a, cfg, s);
     case P2_DIVKGRAD_DIAG: return launch_kind<T, P2_DIVKGRAD_DIAG, 0>(a, cfg, s);
     case P2_DIVKGRAD_GRADK: return launch_kind<T, P2_DIVKGRAD_GRADK, 0>(a, cfg, s);

@@ -81,11 +81,11 @@ __host__ __device__ inline int zero_pattern(int i, int j, int k, int N) {
   return (N - i - j - k == 0) | ((i == 0) << 1) | ((j == 0) << 2) | ((k == 0) << 3);
 }
 
-enum Kind { P1_LAPLACE = 0, P1_DIVKGRAD = 1, P2_LAPLACE = 2, P2_DIVKGRAD = 3, P2V_EPSILON = 4 };
+enum Kind { P1_LAPLACE = 0, P1_DIVKGRAD = 1, P2_LAPLACE = 2, P2_DIVKGRAD = 3, P2V_EPSILON = 4, N1_CURLCURL = 5 };
 // element-kernel modes besides the applies: diag(A) of a scalar P2 kind, and
 // the coefficient gradients gk_b = gy . (dA/dk_b) x of P2 div(k grad) and of
 // the epsilon operator (k = mu)
-enum KernelMode { P2_LAPLACE_DIAG = 5, P2_DIVKGRAD_DIAG = 6, P2_DIVKGRAD_GRADK = 7, P2V_EPSILON_GRADMU = 8 };
+enum KernelMode { P2_LAPLACE_DIAG = 16, P2_DIVKGRAD_DIAG = 17, P2_DIVKGRAD_GRADK = 18, P2V_EPSILON_GRADMU = 19 };
 
 template <typename T>
 struct LatticeArgs {
@@ -124,6 +124,7 @@ struct InstDesc {
   int64_t off;                  // offset of the instance in the concatenated vectors
   int64_t n_local;              // component stride of the instance's vector fields
   const uint32_t *bnd;          // per macro boundary table
+  const int8_t *sign;           // N1: per slot, global / lattice orientation of its edge (NULL otherwise)
   const TypeGeo<T> *geo;        // per macro x 6 types
   const MacroGeo<T> *mgeo;      // per macro (curved maps)
   T *partial;                   // tile partial sums of seam points: [tile][component][box point]

@@ -11,14 +11,16 @@ import torch
 from . import _lib
 from ._lib import check, lib, release
 
-P1_LAPLACE, P1_DIVKGRAD, P2_LAPLACE, P2_DIVKGRAD, P2V_EPSILON = range(5)
+P1_LAPLACE, P1_DIVKGRAD, P2_LAPLACE, P2_DIVKGRAD, P2V_EPSILON, N1_CURLCURL = range(6)
 F64, F32 = 0, 1
 BC_NONE, BC_DIRICHLET_ZERO = 0, 1
 MAP_AFFINE, MAP_SHELL_RADIAL = 0, 1
 
 KIND_NAMES = {P1_LAPLACE: "p1_laplace", P1_DIVKGRAD: "p1_divkgrad", P2_LAPLACE: "p2_laplace",
-              P2_DIVKGRAD: "p2_divkgrad", P2V_EPSILON: "p2v_epsilon"}
-SPACE = {P1_LAPLACE: 1, P1_DIVKGRAD: 1, P2_LAPLACE: 2, P2_DIVKGRAD: 2, P2V_EPSILON: 2}
+              P2_DIVKGRAD: "p2_divkgrad", P2V_EPSILON: "p2v_epsilon", N1_CURLCURL: "n1_curlcurl"}
+SPACE = {P1_LAPLACE: 1, P1_DIVKGRAD: 1, P2_LAPLACE: 2, P2_DIVKGRAD: 2, P2V_EPSILON: 2, N1_CURLCURL: 2}
+# values per slot of the coefficient vector (N1: alpha, then beta)
+COEFF_COMPS = {N1_CURLCURL: 2}
 DTYPE = {F64: torch.float64, F32: torch.float32}
 
 
@@ -99,6 +101,7 @@ class Operator:
         self.has_coeff = bool(hc.value)
         self.space = SPACE[self.kind]
         self.dtype = DTYPE[self.prec]
+        self.coeff_comps = COEFF_COMPS.get(self.kind, 1)
 
     @property
     def handle(self):
@@ -116,7 +119,7 @@ class Operator:
     def apply(self, x, coeff=None, out=None):
         """Enqueue y = A(coeff) x on the current stream of x's device; returns y."""
         px = self._vec(x, "x", self.ncomp)
-        pk = self._vec(coeff, "coeff", 1) if self.has_coeff else None
+        pk = self._vec(coeff, "coeff", self.coeff_comps) if self.has_coeff else None
         if not self.has_coeff and coeff is not None:
             raise ValueError("this operator takes no coefficient")
         if out is None:
@@ -129,7 +132,7 @@ class Operator:
     def apply_local(self, x, coeff=None, out=None):
         """Macro-local partial sums (the apply without the interface sum)."""
         px = self._vec(x, "x", self.ncomp)
-        pk = self._vec(coeff, "coeff", 1) if self.has_coeff else None
+        pk = self._vec(coeff, "coeff", self.coeff_comps) if self.has_coeff else None
         if out is None:
             out = torch.empty_like(x)
         py = self._vec(out, "out", self.ncomp)
