@@ -15,7 +15,8 @@ workloads (P1 Laplacian at levels 4 and 9, the P1 div(k grad) forward and
 fused adjoint at levels 7 and 9, the P2 FP32 apply, the P2 FP64 apply at
 level 7, the P2 div(k grad) adjoint on the headline workload, the vector
 epsilon operator on the radially blended shell in FP64 and FP32 and its
-FP64 adjoint) and the
+FP64 adjoint, the N1 curl-curl + mass operator on the cube at level 6 in FP64
+and FP32) and the
 batched FP32-in-FP64 refinement solve (Jacobi-preconditioned and plain).
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
@@ -48,6 +49,7 @@ FLOPS = {
     "p2_adjoint": 946,         # per micro-tet: forward apply of gy (358) + coefficient gradient (588:
                                # gradient coefficients 40, h 72, Gam 44, M 112, 10 x 16-term contractions 320)
     "eps_affine": 970,         # per micro-tet
+    "n1": 440,                 # per micro-tet: 6 curls, curl u, curl part, U_p, B (beta weights), V, mass part
     "eps_blended_per_q": 657,  # per micro-tet and quadrature point (map Jacobian, inverse, 2 x 90-term contractions)
     "eps_blended_adjoint_per_q": 1337,  # forward of gy (657) + mu gradient (680: map Jacobian and inverse,
                                         # gradients of x and gy, strain contraction, 10-node scatter)
@@ -109,6 +111,8 @@ def device_inputs(mesh, op, seed, torch, kind_family):
         k = W.fields.perturbed_k(keys, 5)
     elif kind_family == "eps":
         k = W.fields.shell_mu(keys, xyz, 3)
+    elif kind_family == "n1":
+        k = W.fields.n1_coeff(xyz)
     else:
         k = None
     dt = op.dtype
@@ -338,7 +342,8 @@ def main():
     if not args.main_only:
         forms = {}
 
-        def form(name, mesh, op, fam, seed, flops_launch, bytes_launch, peak_flops, steps, adjoint=False):
+        def form(name, mesh, op, fam, seed, flops_launch, bytes_launch, peak_flops, steps, adjoint=False,
+                 dofs=None):
             xx, kk = device_inputs(mesh, op, seed, torch, fam)
             yy = torch.empty_like(xx)
             if op.space == 2:
@@ -363,7 +368,8 @@ def main():
                     if a is not None:
                         hip.L.hipEventRecord(a, st)
             w, kms = time_apply(op, xx, kk, yy, steps, 3, hip, torch, fn)
-            r = {"dofs": op.n_unique * op.ncomp, "mdofs": round(op.n_unique * op.ncomp / (w * 1e-3) / 1e6, 2),
+            nd = dofs if dofs is not None else op.n_unique * op.ncomp
+            r = {"dofs": nd, "mdofs": round(nd / (w * 1e-3) / 1e6, 2),
                  "ms_per_apply": round(w, 5), "kernel_ms": round(kms, 5),
                  "hbm_frac": round(bytes_launch / (kms * 1e-3) / PEAK_HBM, 4),
                  "alu_frac": round(flops_launch / (kms * 1e-3) / peak_flops, 4)}
@@ -393,6 +399,15 @@ def main():
         form("p2_divkgrad_fp64_cube_l7", m7, o7, "p2_divkgrad", 2, n_elements(6, 7) * FLOPS["p2_divkgrad"],
              24 * o7.n_local, PEAK_FP64, args.form_steps)
         del o7, m7
+        # N1 curl-curl + mass on the cube, level 6: DoFs = edges (unique P2 slots minus vertices);
+        # bytes: x, y (8 B) and the orientation sign (1 B) per slot, alpha and beta per vertex slot
+        nv_local, nv_unique = mesh.layout(1)
+        for prec, nm, pk, bpd in ((T.F64, "fp64", PEAK_FP64, 8), (T.F32, "fp32", PEAK_FP32, 4)):
+            on = T.Operator(mesh, T.N1_CURLCURL, prec)
+            form("n1_curlcurl_%s_cube_l6" % nm, mesh, on, "n1", 5, nel * FLOPS["n1"],
+                 (2 * bpd + 1) * on.n_local + 2 * bpd * nv_local, pk, args.form_steps,
+                 dofs=on.n_unique - nv_unique)
+            del on
         # P2 adjoint (gx = L(k) gy and gk), two element launches + two seam reductions;
         # 48 B per slot (gy, k -> gx; x, gy -> gk)
         o6a = T.Operator(mesh, T.P2_DIVKGRAD, T.F64)

@@ -20,10 +20,7 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def n1_coeff(xyz):
-    alpha = 1 + 0.5 * np.sin(2 * np.pi * xyz[:, 0]) * np.cos(np.pi * xyz[:, 1]) + 0.2 * xyz[:, 2]
-    beta = 0.6 + 0.3 * np.cos(np.pi * (xyz[:, 0] + 2 * xyz[:, 2]))
-    return np.concatenate([alpha, beta])
+n1_coeff = W.fields.n1_coeff
 
 
 def lib_n1(mesh, level, bc, prec):

@@ -46,3 +46,11 @@ def batch_k_params(count=32, seed=10):
 def batch_k(xyz, a, phi):
     """k_i(x) = 1 + 0.5 sin(2 pi a_i.x + phi_i) for one instance."""
     return 1.0 + 0.5 * np.sin(2 * np.pi * (xyz @ a) + phi)
+
+
+def n1_coeff(xyz):
+    """alpha and beta of the N1 curl-curl + mass operator at node positions, concatenated
+    (smooth and positive; the operator reads them at the vertex points)."""
+    alpha = 1 + 0.5 * np.sin(2 * np.pi * xyz[:, 0]) * np.cos(np.pi * xyz[:, 1]) + 0.2 * xyz[:, 2]
+    beta = 0.6 + 0.3 * np.cos(np.pi * (xyz[:, 0] + 2 * xyz[:, 2]))
+    return np.concatenate([alpha, beta])
