@@ -16,7 +16,7 @@ fused adjoint at levels 7 and 9, the P2 FP32 apply, the P2 FP64 apply at
 level 7, the P2 div(k grad) adjoint on the headline workload, the vector
 epsilon operator on the radially blended shell in FP64 and FP32 and its
 FP64 adjoint, the N1 curl-curl + mass operator on the cube at level 6 in FP64
-and FP32) and the
+and FP32, the stored-local-matrix apply on the headline workload) and the
 batched FP32-in-FP64 refinement solve (Jacobi-preconditioned and plain).
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
@@ -50,6 +50,7 @@ FLOPS = {
                                # gradient coefficients 40, h 72, Gam 44, M 112, 10 x 16-term contractions 320)
     "eps_affine": 970,         # per micro-tet
     "n1": 440,                 # per micro-tet: 6 curls, curl u, curl part, U_p, B (beta weights), V, mass part
+    "p2_stored": 200,          # per micro-tet: symmetric 10 x 10 matrix-vector product from 55 stored entries
     "eps_blended_per_q": 657,  # per micro-tet and quadrature point (map Jacobian, inverse, 2 x 90-term contractions)
     "eps_blended_adjoint_per_q": 1337,  # forward of gy (657) + mu gradient (680: map Jacobian and inverse,
                                         # gradients of x and gy, strain contraction, 10-node scatter)
@@ -408,6 +409,32 @@ def main():
                  (2 * bpd + 1) * on.n_local + 2 * bpd * nv_local, pk, args.form_steps,
                  dofs=on.n_unique - nv_unique)
             del on
+        # stored local matrices (the precomputed-matrix comparison) on the headline workload:
+        # 55 FP64 entries per micro-tet streamed from HBM, plus x and y
+        ost = T.Operator(mesh, T.P2_DIVKGRAD, T.F64)
+        xs_, ks_ = device_inputs(mesh, ost, 2, torch, "p2_divkgrad")
+        ost.store_matrices(ks_)
+        ys_ = torch.empty_like(xs_)
+        Ls = T.lib()
+        sts = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+        def fn_stored(b, a):
+            if b is not None:
+                hip.L.hipEventRecord(b, sts)
+            T.check(Ls.tmf_apply_stored(ost.handle, ctypes.c_void_p(xs_.data_ptr()), ctypes.c_void_p(ys_.data_ptr()),
+                                        sts))
+            if a is not None:
+                hip.L.hipEventRecord(a, sts)
+        w_s, k_s = time_apply(ost, xs_, ks_, ys_, args.form_steps, 3, hip, torch, fn_stored)
+        b_s = 55 * 8 * nel + 16 * ost.n_local
+        forms["p2_divkgrad_stored_matrices_fp64_cube_l6"] = {
+            "dofs": ost.n_unique, "mdofs": round(ost.n_unique / (w_s * 1e-3) / 1e6, 2), "ms_per_apply": round(w_s, 5),
+            "kernel_ms": round(k_s, 5), "stored_bytes": 55 * 8 * nel,
+            "hbm_frac": round(b_s / (k_s * 1e-3) / PEAK_HBM, 4),
+            "alu_frac": round(nel * FLOPS["p2_stored"] / (k_s * 1e-3) / PEAK_FP64, 4),
+            "matrix_free_speedup": round(w_s / wall, 2)}
+        log("p2_divkgrad_stored_matrices_fp64_cube_l6", forms["p2_divkgrad_stored_matrices_fp64_cube_l6"])
+        del ost, xs_, ks_, ys_
         # P2 adjoint (gx = L(k) gy and gk), two element launches + two seam reductions;
         # 48 B per slot (gy, k -> gx; x, gy -> gk)
         o6a = T.Operator(mesh, T.P2_DIVKGRAD, T.F64)

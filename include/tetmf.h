@@ -207,6 +207,20 @@ tmf_status tmf_interface_sum(tmf_op *op, void *v, tmf_stream stream);
  * than TMF_P2_LAPLACE and TMF_P2_DIVKGRAD return TMF_EUNSUPPORTED. */
 tmf_status tmf_diagonal(tmf_op *op, const void *coeff, void *d, tmf_stream stream);
 
+/* The precomputed-matrix alternative to the matrix-free apply (the paper's
+ * comparison of matrix-free kernels with stored local matrices, section
+ * "Matrix-Free Finite Elements"): tmf_op_store_matrices evaluates every
+ * micro-tet's symmetric 10 x 10 local matrix A_T(coeff) of TMF_P2_DIVKGRAD
+ * once and keeps its 55 upper-triangle entries in device memory owned by the
+ * op (about 55 * 8 bytes per micro-tet in FP64, allocated here; laid out per
+ * tile, type and entry with the box's cubes contiguous, for the tile shape
+ * current at this call); tmf_apply_stored then computes y = A x from them
+ * (same result as tmf_apply with that coeff, up to rounding).  Both are
+ * asynchronous on `stream`; tmf_apply_stored allocates nothing.  Errors:
+ * TMF_EUNSUPPORTED for other kinds; TMF_EINVAL if nothing is stored. */
+tmf_status tmf_op_store_matrices(tmf_op *op, const void *coeff, tmf_stream stream);
+tmf_status tmf_apply_stored(tmf_op *op, const void *x, void *y, tmf_stream stream);
+
 /* Reverse mode of the macro-local apply of TMF_P1_DIVKGRAD, TMF_P2_DIVKGRAD
  * and TMF_P2V_EPSILON (FP64 or FP32; for epsilon k is mu, and x, gy, gx hold
  * 3 * n_local values while coeff and gk hold n_local).

@@ -35,6 +35,8 @@ SIGNATURES = [
     ("tmf_apply_local", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     ("tmf_interface_sum", c_int, [c_vp, c_vp, c_vp]),
     ("tmf_diagonal", c_int, [c_vp, c_vp, c_vp, c_vp]),
+    ("tmf_op_store_matrices", c_int, [c_vp, c_vp, c_vp]),
+    ("tmf_apply_stored", c_int, [c_vp, c_vp, c_vp, c_vp]),
     ("tmf_op_num_tiles", c_int, [c_vp, ctypes.POINTER(c_int)]),
     ("tmf_op_tile_shape", c_int, [c_vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
                                   ctypes.POINTER(c_int)]),

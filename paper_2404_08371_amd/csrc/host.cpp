@@ -687,12 +687,14 @@ GroupArgs group_args(const tmf_op *op) {
 template <typename T>
 hipError_t tile_path(tmf_op *op, int kind, const void *coeff, const void *x, T *yy, hipStream_t s, hipEvent_t ev0,
                      hipEvent_t ev1, bool interface, const void *x2 = nullptr, int seam_flags = 0,
-                     int ncomp_out = 0) {
+                     int ncomp_out = 0, void *mat = nullptr, int cfg = -1, bool gather = true) {
   hipError_t e;
+  const int c = cfg >= 0 ? cfg : op->tile_cfg;
   TileArgs<T> a;
   a.inst = reinterpret_cast<const InstDesc<T> *>(op->desc.p);
-  a.tiles = op->tiles[op->tile_cfg].p;
-  a.ntiles = op->ntiles[op->tile_cfg];
+  a.tiles = op->tiles[c].p;
+  a.ntiles = op->ntiles[c];
+  a.mat = static_cast<T *>(mat);
   a.active = nullptr;
   a.qtab = reinterpret_cast<const T *>(op->qtab.p);
   a.nq = op->nq;
@@ -701,10 +703,9 @@ hipError_t tile_path(tmf_op *op, int kind, const void *coeff, const void *x, T *
   a.x2 = static_cast<const T *>(x2);
   a.y = yy;
   if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
-  e = launch_tile_apply<T>(a, kind, op->mesh->map, op->tile_cfg, s);
+  e = launch_tile_apply<T>(a, kind, op->mesh->map, c, s);
   if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
-  const int c = op->tile_cfg;
-  if (e == hipSuccess)
+  if (e == hipSuccess && gather)
     e = launch_seam_gather<T>(reinterpret_cast<const SeamInst<T> *>(op->seaminst[c].p),
                               op->seamwork[c].p + (interface ? 0 : op->ngroupwork[c]),
                               interface ? op->nseamwork[c] : op->nseamonly[c], yy, nullptr,
@@ -814,6 +815,47 @@ tmf_status tmf_diagonal(tmf_op *op, const void *coeff, void *d, tmf_stream strea
                      ? tile_path<double>(op, dk, coeff, d, static_cast<double *>(d), s, nullptr, nullptr, true)
                      : tile_path<float>(op, dk, coeff, d, static_cast<float *>(d), s, nullptr, nullptr, true);
   if (e != hipSuccess) return hip_fail(e, "diagonal launch");
+  return TMF_OK;
+}
+
+tmf_status tmf_op_store_matrices(tmf_op *op, const void *coeff, tmf_stream stream) {
+  if (!op || !coeff) return fail(TMF_EINVAL, "op or coeff is NULL");
+  if (op->kind != TMF_P2_DIVKGRAD)
+    return fail(TMF_EUNSUPPORTED, "stored local matrices are provided for TMF_P2_DIVKGRAD");
+  const int cfg = op->tile_cfg;
+  const size_t esz = op->prec == TMF_F64 ? 8 : 4;
+  const size_t cubes = static_cast<size_t>(kTileCfg[cfg][0]) * kTileCfg[cfg][1] * kTileCfg[cfg][2];
+  const size_t bytes = static_cast<size_t>(op->ntiles[cfg]) * 6 * kStoredEntries * cubes * esz;
+  if (op->mat.n != bytes) {
+    op->mat_cfg = -1;
+    tmf_status st = op->mat.alloc(bytes);
+    if (st != TMF_OK) return st;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the store mode reads only k and writes only the matrices (no x, no y,
+  // no gather); coeff stands in for the unused vector pointers
+  hipError_t e =
+      op->prec == TMF_F64
+          ? tile_path<double>(op, P2_DIVKGRAD_STORE, coeff, coeff, const_cast<double *>(static_cast<const double *>(coeff)),
+                              s, nullptr, nullptr, true, nullptr, 0, 0, op->mat.p, cfg, false)
+          : tile_path<float>(op, P2_DIVKGRAD_STORE, coeff, coeff, const_cast<float *>(static_cast<const float *>(coeff)),
+                             s, nullptr, nullptr, true, nullptr, 0, 0, op->mat.p, cfg, false);
+  if (e != hipSuccess) return hip_fail(e, "matrix store launch");
+  op->mat_cfg = cfg;
+  return TMF_OK;
+}
+
+tmf_status tmf_apply_stored(tmf_op *op, const void *x, void *y, tmf_stream stream) {
+  if (!op || !x || !y) return fail(TMF_EINVAL, "op, x or y is NULL");
+  if (op->mat_cfg < 0) return fail(TMF_EINVAL, "no stored matrices: call tmf_op_store_matrices first");
+  if (x == y) return fail(TMF_EINVAL, "y must not alias x");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = op->prec == TMF_F64
+                     ? tile_path<double>(op, P2_STORED_APPLY, nullptr, x, static_cast<double *>(y), s, nullptr, nullptr,
+                                         true, nullptr, 0, 0, op->mat.p, op->mat_cfg, true)
+                     : tile_path<float>(op, P2_STORED_APPLY, nullptr, x, static_cast<float *>(y), s, nullptr, nullptr,
+                                        true, nullptr, 0, 0, op->mat.p, op->mat_cfg, true);
+  if (e != hipSuccess) return hip_fail(e, "stored apply launch");
   return TMF_OK;
 }
 

@@ -97,6 +97,8 @@ struct tmf_op {
   DevBuf<int64_t> gpos;                   // per interface-group member: macro << 32 | packed lattice point
   DevBuf<int> gpl;                        // per interface-group member: position << 16 | group size
   DevBuf<int8_t> sign;                    // N1: per slot, global / lattice orientation of its edge (0: vertex)
+  DevBuf<uint8_t> mat;                    // stored local matrices (tmf_op_store_matrices)
+  int mat_cfg = -1;                       // tile shape they were stored for (-1: none)
   int seamrows[kNumTileCfg] = {0};        // tile-row table entries per macro, per tile shape
 };
 

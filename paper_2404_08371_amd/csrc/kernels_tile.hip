@@ -640,11 +640,15 @@ struct TileCfg {
   static constexpr bool GRAD = GRADK || GRADMU;
   static constexpr int NCX = GRADMU ? 3 : GRADK ? 1 : NC;   // components of x
   static constexpr int NCI = GRAD ? 2 * NCX : NC;           // staged input vectors (x, then gy)
-  static constexpr bool HASK = KIND != P2_LAPLACE && KIND != P2_LAPLACE_DIAG && !GRAD;
+  static constexpr bool HASK = KIND != P2_LAPLACE && KIND != P2_LAPLACE_DIAG && !GRAD && KIND != P2_STORED_APPLY;
   // N1: edge DoFs with a per-slot orientation sign; two coefficients (alpha,
   // beta) read at the vertex points
   static constexpr bool N1 = KIND == N1_CURLCURL;
   static constexpr int NK = N1 ? 2 : 1;
+  // stored-matrix modes: STORE builds the local matrices from k (no x, no
+  // output), SAPPLY applies them (x only)
+  static constexpr bool STORE = KIND == P2_DIVKGRAD_STORE, SAPPLY = KIND == P2_STORED_APPLY;
+  static constexpr bool STORED = STORE || SAPPLY;
   // Scalar kinds: WPG wavefronts per workgroup, wavefront w applying the
   // micro-tet types t = w (mod WPG) to every cube of the box, so the type is
   // a compile-time constant inside each loop (LDS node offsets become
@@ -662,9 +666,10 @@ struct TileCfg {
 };
 
 // one micro-tet whose 10 local nodes sit at LDS points li[]
-template <typename T, int KIND, int MAP, int R, int t>
+template <typename T, int KIND, int MAP, int R, int t, int CS>
 __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T> *D, T (*sx)[R], const T *sk,
-                                          double (*sy)[R], const int li[10], int m, int bxc, int byc, int bzc) {
+                                          double (*sy)[R], const int li[10], int m, int bxc, int byc, int bzc,
+                                          T *me) {
   const TypeGeo<T> *g = D->geo + 6 * m + t;
   if constexpr (KIND == P2V_EPSILON) {
     T u[3][10], mu[10], y[3][10];
@@ -693,6 +698,41 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
     for (int v = 0; v < 10; ++v)
 #pragma unroll
       for (int c = 0; c < 3; ++c) atomicAdd(&sy[c][li[v]], double(y[c][v]));
+  } else if constexpr (KIND == P2_DIVKGRAD_STORE) {
+    // columns A e_v of the local matrix; the upper triangle is stored
+    T kv[10], A[10][10];
+#pragma unroll
+    for (int v = 0; v < 10; ++v) kv[v] = sk[li[v]];
+#pragma unroll
+    for (int v = 0; v < 10; ++v) {
+      T u[10];
+#pragma unroll
+      for (int w = 0; w < 10; ++w) u[w] = w == v ? T(1) : T(0);
+      p2_elem<T, true>(u, kv, cptr(g->Gp), A[v]);
+    }
+    int e = 0;
+#pragma unroll
+    for (int i = 0; i < 10; ++i)
+#pragma unroll
+      for (int j = i; j < 10; ++j) me[(e++) * CS] = A[j][i];
+  } else if constexpr (KIND == P2_STORED_APPLY) {
+    T u[10], y[10];
+#pragma unroll
+    for (int v = 0; v < 10; ++v) {
+      u[v] = sx[0][li[v]];
+      y[v] = T(0);
+    }
+    int e = 0;
+#pragma unroll
+    for (int i = 0; i < 10; ++i)
+#pragma unroll
+      for (int j = i; j < 10; ++j) {
+        const T aij = me[(e++) * CS];
+        y[i] += aij * u[j];
+        if (j != i) y[j] += aij * u[i];
+      }
+#pragma unroll
+    for (int v = 0; v < 10; ++v) atomicAdd(&sy[0][li[v]], double(y[v]));
   } else if constexpr (KIND == N1_CURLCURL) {
     T u[6], al[4], be[4], y6[6];
 #pragma unroll
@@ -779,7 +819,7 @@ constexpr int node_off(int t, int v, int RY, int OO, int RXP) {
 // micro-tet of type t in cube c of the box (x fastest), if it exists
 template <typename T, int KIND, int MAP, int TX, int TY, int TZ, int t, int R>
 __device__ __forceinline__ void cube_elem(const TileArgs<T> &a, const InstDesc<T> *D, T (*sx)[R], const T *sk,
-                                          double (*sy)[R], int m, int bx0, int by0, int bz0, int c) {
+                                          double (*sy)[R], int m, int bx0, int by0, int bz0, int c, int tw) {
   using Cfg = TileCfg<T, KIND, MAP, TX, TY, TZ>;
   constexpr int RY = Cfg::RY, OO = Cfg::OO, RXP = Cfg::RXP;
   const int cx = c % TX, cy = (c / TX) % TY, cz = c / (TX * TY);
@@ -788,15 +828,18 @@ __device__ __forceinline__ void cube_elem(const TileArgs<T> &a, const InstDesc<T
   int li[10];
 #pragma unroll
   for (int v = 0; v < 10; ++v) li[v] = cb + node_off(t, v, RY, OO, RXP);
-  tile_elem<T, KIND, MAP, R, t>(a, D, sx, sk, sy, li, m, bx0 + cx, by0 + cy, bz0 + cz);
+  // stored-matrix modes: the element's 55 entries at me[e * C], e = 0..54
+  T *me = Cfg::STORED ? a.mat + (static_cast<int64_t>(tw) * 6 + t) * kStoredEntries * Cfg::C + c : nullptr;
+  tile_elem<T, KIND, MAP, R, t, Cfg::C>(a, D, sx, sk, sy, li, m, bx0 + cx, by0 + cy, bz0 + cz, me);
 }
 
 // every cube of the box, micro-tet type t; lane l takes cubes l, l + 64, ...
 template <typename T, int KIND, int MAP, int TX, int TY, int TZ, int t, int R>
 __device__ __forceinline__ void type_loop(const TileArgs<T> &a, const InstDesc<T> *D, T (*sx)[R], const T *sk,
-                                          double (*sy)[R], int m, int bx0, int by0, int bz0, int lane) {
+                                          double (*sy)[R], int m, int bx0, int by0, int bz0, int lane, int tw) {
   constexpr int C = TX * TY * TZ;
-  for (int c = lane; c < C; c += 64) cube_elem<T, KIND, MAP, TX, TY, TZ, t, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, c);
+  for (int c = lane; c < C; c += 64)
+    cube_elem<T, KIND, MAP, TX, TY, TZ, t, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tw);
 }
 
 // One workgroup per tile.  Workgroup ids are dispatched round-robin over the
@@ -875,7 +918,7 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
       if (qi <= lim) {
         const int off = srb[row] + qi;
         const int zp = (qi == lim) | ((qi == 0) << 1) | (info & 12);
-        if (!Cfg::DIAG && !((bnd >> zp) & 1u)) {
+        if (!Cfg::DIAG && !Cfg::STORE && !((bnd >> zp) & 1u)) {
 #pragma unroll
           for (int c = 0; c < NCI; ++c) xv[p][c] = xb[c][off];
         }
@@ -918,27 +961,28 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
     // wavefront w applies the types t = w (mod WPG) to every cube
     constexpr int WPG = Cfg::WPG;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-    if (0 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 0, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane);
-    if (1 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 1, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane);
-    if (2 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 2, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane);
-    if (3 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 3, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane);
-    if (4 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 4, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane);
-    if (5 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 5, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane);
+    if (0 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 0, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane, tl.w);
+    if (1 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 1, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane, tl.w);
+    if (2 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 2, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane, tl.w);
+    if (3 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 3, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane, tl.w);
+    if (4 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 4, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane, tl.w);
+    if (5 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 5, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane, tl.w);
   } else {
     // slot e -> (type e / C, cube e % C); 64 | C makes the type wave-uniform
     constexpr int C = Cfg::C;
     for (int e = tid; e < 6 * C; e += NTH) {
       const int t = __builtin_amdgcn_readfirstlane(e / C), c = e - t * C;
       switch (t) {
-        case 0: cube_elem<T, KIND, MAP, TX, TY, TZ, 0, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
-        case 1: cube_elem<T, KIND, MAP, TX, TY, TZ, 1, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
-        case 2: cube_elem<T, KIND, MAP, TX, TY, TZ, 2, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
-        case 3: cube_elem<T, KIND, MAP, TX, TY, TZ, 3, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
-        case 4: cube_elem<T, KIND, MAP, TX, TY, TZ, 4, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
-        default: cube_elem<T, KIND, MAP, TX, TY, TZ, 5, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c); break;
+        case 0: cube_elem<T, KIND, MAP, TX, TY, TZ, 0, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w); break;
+        case 1: cube_elem<T, KIND, MAP, TX, TY, TZ, 1, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w); break;
+        case 2: cube_elem<T, KIND, MAP, TX, TY, TZ, 2, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w); break;
+        case 3: cube_elem<T, KIND, MAP, TX, TY, TZ, 3, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w); break;
+        case 4: cube_elem<T, KIND, MAP, TX, TY, TZ, 4, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w); break;
+        default: cube_elem<T, KIND, MAP, TX, TY, TZ, 5, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w); break;
       }
     }
   }
+  if constexpr (Cfg::STORE) return;  // the matrices are the output
   __syncthreads();
 
   // 3. write back: points of this box alone go to y (Dirichlet DoFs as 0),
@@ -1158,6 +1202,8 @@ hipError_t launch_tile_apply(const TileArgs<T> &a, int kind, int map, int cfg, h
     case P2_LAPLACE: return launch_kind<T, P2_LAPLACE, 0>(a, cfg, s);
     case P2_DIVKGRAD: return launch_kind<T, P2_DIVKGRAD, 0>(a, cfg, s);
     case N1_CURLCURL: return launch_kind<T, N1_CURLCURL, 0>(a, cfg, s);
+    case P2_DIVKGRAD_STORE: return launch_kind<T, P2_DIVKGRAD_STORE, 0>(a, cfg, s);
+    case P2_STORED_APPLY: return launch_kind<T, P2_STORED_APPLY, 0>(a, cfg, s);
     case P2_LAPLACE_DIAG: return launch_kind<T, P2_LAPLACE_DIAG, 0>(a, cfg, s);
     case P2_DIVKGRAD_DIAG: return launch_kind<T, P2_DIVKGRAD_DIAG, 0>(a, cfg, s);
     case P2_DIVKGRAD_GRADK: return launch_kind<T, P2_DIVKGRAD_GRADK, 0>(a, cfg, s);

@@ -85,7 +85,18 @@ enum Kind { P1_LAPLACE = 0, P1_DIVKGRAD = 1, P2_LAPLACE = 2, P2_DIVKGRAD = 3, P2
 // element-kernel modes besides the applies: diag(A) of a scalar P2 kind, and
 // the coefficient gradients gk_b = gy . (dA/dk_b) x of P2 div(k grad) and of
 // the epsilon operator (k = mu)
-enum KernelMode { P2_LAPLACE_DIAG = 16, P2_DIVKGRAD_DIAG = 17, P2_DIVKGRAD_GRADK = 18, P2V_EPSILON_GRADMU = 19 };
+enum KernelMode {
+  P2_LAPLACE_DIAG = 16,
+  P2_DIVKGRAD_DIAG = 17,
+  P2_DIVKGRAD_GRADK = 18,
+  P2V_EPSILON_GRADMU = 19,
+  // stored local matrices (the precomputed-matrix comparison): build them
+  // from k, or apply them
+  P2_DIVKGRAD_STORE = 20,
+  P2_STORED_APPLY = 21
+};
+// entries of a stored symmetric 10 x 10 local matrix (upper triangle, row-major)
+constexpr int kStoredEntries = 55;
 
 template <typename T>
 struct LatticeArgs {
@@ -144,6 +155,7 @@ struct TileArgs {
   const T *k;
   const T *x;
   const T *x2 = nullptr;  // second staged input (gy of the coefficient-gradient mode)
+  T *mat = nullptr;       // stored local matrices [tile][type][entry][cube]
   T *y;
 };
 

@@ -152,6 +152,21 @@ class Operator:
             check(lib().tmf_diagonal(self._h, pk, pd, _stream_handle(out.device)))
         return out
 
+    def store_matrices(self, coeff):
+        """Evaluate and keep every micro-tet's local matrix A_T(coeff) (P2 div(k grad))."""
+        pk = self._vec(coeff, "coeff", 1)
+        with torch.cuda.device(coeff.device):
+            check(lib().tmf_op_store_matrices(self._h, pk, _stream_handle(coeff.device)))
+
+    def apply_stored(self, x, out=None):
+        """y = A x from the stored local matrices."""
+        px = self._vec(x, "x", 1)
+        if out is None:
+            out = torch.empty_like(x)
+        with torch.cuda.device(x.device):
+            check(lib().tmf_apply_stored(self._h, px, self._vec(out, "out", 1), _stream_handle(x.device)))
+        return out
+
     def interface_sum_(self, v):
         """In place: every copy of a shared DoF gets the sum over its copies."""
         pv = self._vec(v, "v", self.ncomp)
