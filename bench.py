@@ -80,6 +80,7 @@ class Hip:
         self.L.hipEventDestroy.argtypes = [ctypes.c_void_p]
         self.L.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
                                                ctypes.c_void_p]
+        self.L.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
 
     def event(self):
         e = ctypes.c_void_p()
@@ -133,17 +134,32 @@ def sampled_events(hip, steps):
     return [(hip.event(), hip.event()) if i % EVENT_EVERY == 0 else (None, None) for i in range(steps)]
 
 
-def kernel_mean_ms(hip, evs):
-    """Mean element-kernel duration over the sampled steps; releases the events."""
+def kernel_mean_ms(hip, evs, stats=None):
+    """Mean element-kernel duration over the sampled steps (median and minimum into `stats`);
+    releases the events."""
     ms = [hip.elapsed_ms(b, a) for b, a in evs if b is not None]
     for b, a in evs:
         if b is not None:
             hip.destroy(b)
             hip.destroy(a)
+    if stats is not None:
+        stats["kernel_ms_median"] = round(float(np.median(ms)), 5)
+        stats["kernel_ms_min"] = round(float(np.min(ms)), 5)
     return float(np.mean(ms))
 
 
-def time_apply(op, x, k, y, steps, warmup, hip, torch, fn=None):
+def clock_state():
+    """Current GPU clocks as rocm-smi reports them (None when it is not available)."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=20)
+    except (OSError, subprocess.SubprocessError):
+        return None
+    lines = [ln.strip() for ln in r.stdout.splitlines() if "clock level" in ln.lower() or "Mhz" in ln]
+    return lines[:8] or None
+
+
+def time_apply(op, x, k, y, steps, warmup, hip, torch, fn=None, stats=None):
     """Warm up, then time exactly `steps` applies; returns (wall ms/step, kernel ms mean)."""
     import paper_2404_08371_amd as T
     L = T.lib()
@@ -162,7 +178,7 @@ def time_apply(op, x, k, y, steps, warmup, hip, torch, fn=None):
             fn(b, a)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / steps
-    return wall, kernel_mean_ms(hip, evs)
+    return wall, kernel_mean_ms(hip, evs, stats)
 
 
 def n_elements(mesh_nt, level):
@@ -309,7 +325,30 @@ def main():
     tx, ty, tz = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     T.check(T.lib().tmf_op_tile_shape(op.handle, cfg.value, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(tz)))
     log("autotuned tile", (tx.value, ty.value, tz.value), "%.4f ms" % ms.value)
-    wall, kern = time_apply(op, x, k, y, args.steps, args.warmup, hip, torch)
+    kstats = {}
+    wall, kern = time_apply(op, x, k, y, args.steps, args.warmup, hip, torch, stats=kstats)
+    # cold variant: a 512 MB write before each apply evicts the 256 MB last-level
+    # cache (the headline's 52.7 MB of inputs fit in it); element kernel and whole
+    # apply timed with events around each call
+    scratch = torch.empty(1 << 26, dtype=torch.float64, device="cuda")
+    L0 = T.lib()
+    st0 = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    cold_k, cold_s = [], []
+    for _ in range(10):
+        scratch.fill_(1.0)
+        e0, e1, e2, e3 = hip.event(), hip.event(), hip.event(), hip.event()
+        hip.L.hipEventRecord(e0, st0)
+        T.check(L0.tmf_apply_timed(op.handle, ctypes.c_void_p(k.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                   ctypes.c_void_p(y.data_ptr()), st0, e1, e2))
+        hip.L.hipEventRecord(e3, st0)
+        torch.cuda.synchronize()
+        cold_k.append(hip.elapsed_ms(e1, e2))
+        cold_s.append(hip.elapsed_ms(e0, e3))
+        for e in (e0, e1, e2, e3):
+            hip.destroy(e)
+    del scratch
+    kstats["cold_kernel_ms_median"] = round(float(np.median(cold_k)), 5)
+    kstats["cold_step_ms_median"] = round(float(np.median(cold_s)), 5)
     nel = n_elements(6, 6)
     flops = nel * FLOPS["p2_divkgrad"]
     bytes_alg = 3 * op.n_local * 8
@@ -335,7 +374,8 @@ def main():
                      "kernel_ms": round(kern, 5), "flops_per_launch": flops,
                      "alg_bytes_per_launch": bytes_alg,
                      "hbm_frac": round(bytes_alg / (kern * 1e-3) / PEAK_HBM, 4),
-                     "device_copy_GBps": round(copy_gbs, 1)},
+                     "device_copy_GBps": round(copy_gbs, 1), **kstats},
+        "clocks": clock_state(),
     }
     log("headline %.1f MDoF/s, kernel %.4f ms, step %.4f ms" % (value, kern, wall))
 
@@ -378,7 +418,6 @@ def main():
             log(name, r)
             del xx, kk, yy
 
-        hip.L.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         vr, tr = W.meshes.ref_tet()
         for lvl in (4, 9):
             m1 = T.Mesh(vr, tr, lvl)
