@@ -152,6 +152,9 @@ class Problem:
         if k == P2_LAPLACE:
             return el.p2_laplace(P)
         if k == P2_DIVKGRAD:
+            # with a rule on an affine mesh: the quadrature (under-integration) variant
+            if self.qbary is not None and self.map == MAP_AFFINE:
+                return el.p2_divkgrad_quad(P, c_e, self.qbary, self.qw)
             return el.p2_divkgrad(P, c_e)
         if self.map == MAP_AFFINE:
             return el.eps_affine(P, c_e)

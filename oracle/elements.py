@@ -176,6 +176,19 @@ def p2_divkgrad(P, k):
     return vol[..., None, None] * np.einsum("...m,...mji->...ji", np.asarray(k), T)
 
 
+def p2_divkgrad_quad(P, k, qbary, qw):
+    """P2 div(k grad) integrated with a quadrature rule on the reference tet
+    (weights summing to 1/6): A_ji = 6 |T| sum_q w_q k(q) grad(phi_i).grad(phi_j) at q,
+    k nodal P2.  Exact for rules of degree >= 4; the paper's under-integrated
+    variant uses a degree-2 rule (section "Variable-Coefficient Diffusion")."""
+    vol, g = geometry(P)
+    vals, dv = p2_eval(qbary)                       # (nq,10), (nq,10,4)
+    kq = np.einsum("...m,qm->...q", np.asarray(k), vals)
+    grads = np.einsum("qia,...ad->...qid", dv, g)    # (...,nq,10,3)
+    A = np.einsum("q,...q,...qjd,...qid->...ji", np.asarray(qw), kq, grads, grads)
+    return 6.0 * vol[..., None, None] * A
+
+
 def _strain_pairs(g):
     """S[a,c,b,d] = 2 sym(e_c (x) g_a) : sym(e_d (x) g_b) for gradient vectors g (...,4,3)."""
     eye = np.eye(3)
