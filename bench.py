@@ -16,7 +16,8 @@ fused adjoint at levels 7 and 9, the P2 FP32 apply, the P2 FP64 apply at
 level 7, the P2 div(k grad) adjoint on the headline workload, the vector
 epsilon operator on the radially blended shell in FP64 and FP32 and its
 FP64 adjoint, the N1 curl-curl + mass operator on the cube at level 6 in FP64
-and FP32, the stored-local-matrix apply on the headline workload) and the
+and FP32, the stored-local-matrix apply and the degree-2 quadrature variant
+on the headline workload) and the
 batched FP32-in-FP64 refinement solve (Jacobi-preconditioned and plain).
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
@@ -51,6 +52,8 @@ FLOPS = {
     "eps_affine": 970,         # per micro-tet
     "n1": 440,                 # per micro-tet: 6 curls, curl u, curl part, U_p, B (beta weights), V, mass part
     "p2_stored": 200,          # per micro-tet: symmetric 10 x 10 matrix-vector product from 55 stored entries
+    "p2_quad_per_q": 60,       # per micro-tet and quadrature point: k(q) (10 FMA) and 10 weight updates
+    "p2_no_weights": 266,      # per micro-tet: the P2 div(k grad) apply without its exact weights (358 - 92)
     "eps_blended_per_q": 657,  # per micro-tet and quadrature point (map Jacobian, inverse, 2 x 90-term contractions)
     "eps_blended_adjoint_per_q": 1337,  # forward of gy (657) + mu gradient (680: map Jacobian and inverse,
                                         # gradients of x and gy, strain contraction, 10-node scatter)
@@ -448,6 +451,12 @@ def main():
                  (2 * bpd + 1) * on.n_local + 2 * bpd * nv_local, pk, args.form_steps,
                  dofs=on.n_unique - nv_unique)
             del on
+        # quadrature (under-integration) variant with the 4-point degree-2 rule, headline workload
+        oq = T.Operator(mesh, T.P2_DIVKGRAD, T.F64, rule=W.quadrature.rule_degree2())
+        form("p2_divkgrad_quad_degree2_fp64_cube_l6", mesh, oq, "p2_divkgrad", 2,
+             nel * (FLOPS["p2_no_weights"] + 4 * FLOPS["p2_quad_per_q"]), 24 * oq.n_local, PEAK_FP64,
+             args.form_steps)
+        del oq
         # stored local matrices (the precomputed-matrix comparison) on the headline workload:
         # 55 FP64 entries per micro-tet streamed from HBM, plus x and y
         ost = T.Operator(mesh, T.P2_DIVKGRAD, T.F64)

@@ -164,8 +164,14 @@ tmf_status tmf_mesh_dof_info(const tmf_mesh *mesh, int space, int64_t *keys, dou
  *   qbary, qw, nq   quadrature rule on the reference tet (host arrays: nq x 4
  *          barycentric coordinates, nq weights summing to 1/6).  Required
  *          (1 <= nq <= TMF_MAX_QUAD) for the blended shell map, which only the
- *          epsilon operator supports; must be NULL/NULL/0 for affine meshes,
- *          whose forms are integrated exactly.
+ *          epsilon operator supports.  On affine meshes forms are integrated
+ *          exactly and the rule must be NULL/NULL/0, except for
+ *          TMF_P2_DIVKGRAD, where a rule selects its quadrature variant:
+ *          weights 6 sum_q w_q k(q) lambda_c(q) lambda_e(q) in place of the
+ *          exact ones (the under-integration option of section
+ *          "Variable-Coefficient Diffusion" with a degree-2 rule; a rule of
+ *          degree >= 4 gives the exact operator).  Diagonal, adjoint, stored
+ *          matrices and batches are provided for the exact operator only.
  * Allocates the operator's device tables on the current HIP device.
  * Errors: TMF_EINVAL (bad enum, level above the space maximum, bad rule),
  * TMF_EUNSUPPORTED (blended map with a scalar kind), TMF_ENOMEM, TMF_EDEVICE. */

@@ -137,7 +137,8 @@ tmf_status tmf_batch_create(tmf_op *const *ops, int count, tmf_batch **out) {
       return fail(TMF_EUNSUPPORTED, "batches hold P2 / epsilon operators (element kernels)");
     if (o->kind != o0->kind || o->prec != o0->prec)
       return fail(TMF_EINVAL, "operator %d differs in kind or precision from operator 0", i);
-    if (o->mesh->map != TMF_MAP_AFFINE) return fail(TMF_EUNSUPPORTED, "batches hold affine meshes");
+    if (o->mesh->map != TMF_MAP_AFFINE || o->nq > 0)
+      return fail(TMF_EUNSUPPORTED, "batches hold exactly integrated operators on affine meshes");
     for (int j = 0; j < i; ++j)
       if (ops[j] == o) return fail(TMF_EINVAL, "operator %d appears twice", i);
   }

@@ -411,11 +411,14 @@ tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const
   const int space = kind <= TMF_P1_DIVKGRAD ? 1 : 2;
   if (space == 2 && mesh->level > TMF_MAX_LEVEL_P2)
     return fail(TMF_EINVAL, "P2 operators support level <= %d", TMF_MAX_LEVEL_P2);
-  if (mesh->map == TMF_MAP_SHELL_RADIAL) {
-    if (kind != TMF_P2V_EPSILON)
+  // a rule defines the blended epsilon operator, or the quadrature
+  // (under-integration) variant of the affine P2 div(k grad) operator
+  const bool quad_variant = mesh->map == TMF_MAP_AFFINE && kind == TMF_P2_DIVKGRAD && (qbary || qw || nq != 0);
+  if (mesh->map == TMF_MAP_SHELL_RADIAL || quad_variant) {
+    if (mesh->map == TMF_MAP_SHELL_RADIAL && kind != TMF_P2V_EPSILON)
       return fail(TMF_EUNSUPPORTED, "the blended shell map is supported for the epsilon operator only");
     if (!qbary || !qw || nq < 1 || nq > TMF_MAX_QUAD)
-      return fail(TMF_EINVAL, "the blended map needs a quadrature rule with 1..%d points", TMF_MAX_QUAD);
+      return fail(TMF_EINVAL, "the quadrature rule needs 1..%d points", TMF_MAX_QUAD);
     double wsum = 0;
     for (int q = 0; q < nq; ++q) {
       double s = 0;
@@ -429,7 +432,7 @@ tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const
     }
     if (std::fabs(wsum - 1.0 / 6.0) > 1e-12) return fail(TMF_EINVAL, "quadrature weights must sum to 1/6");
   } else if (qbary || qw || nq != 0) {
-    return fail(TMF_EINVAL, "affine operators are integrated exactly: pass no quadrature rule");
+    return fail(TMF_EINVAL, "this affine operator is integrated exactly: pass no quadrature rule");
   }
   tmf_mesh *mm = const_cast<tmf_mesh *>(mesh);
   tmf_build_layout(mm, space);
@@ -447,7 +450,7 @@ tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const
   op->L = S.L;
   op->n_local = S.n_local;
   op->n_unique = S.n_unique;
-  op->nq = mesh->map == TMF_MAP_SHELL_RADIAL ? nq : 0;
+  op->nq = (mesh->map == TMF_MAP_SHELL_RADIAL || quad_variant) ? nq : 0;
   tmf_status st = TMF_OK;
   if (prec == TMF_F64) {
     std::vector<TypeGeo<double>> g;
@@ -730,7 +733,8 @@ hipError_t apply_t(tmf_op *op, const void *coeff, const void *x, void *y, hipStr
     e = launch_p1_apply<T>(a, op->kind, op->chunks.p, op->nchunks, s);
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
   } else {
-    return tile_path<T>(op, op->kind, coeff, x, yy, s, ev0, ev1, interface);
+    const int mode = op->kind == TMF_P2_DIVKGRAD && op->nq > 0 ? P2_DIVKGRAD_Q : op->kind;
+    return tile_path<T>(op, mode, coeff, x, yy, s, ev0, ev1, interface);
   }
   if (e != hipSuccess || !interface) return e;
   return launch_interface_sum<T>(group_args(op), yy, s);
@@ -802,8 +806,8 @@ tmf_status tmf_apply_local(tmf_op *op, const void *coeff, const void *x, void *y
 
 tmf_status tmf_diagonal(tmf_op *op, const void *coeff, void *d, tmf_stream stream) {
   if (!op || !d) return fail(TMF_EINVAL, "op or d is NULL");
-  if (op->kind != TMF_P2_LAPLACE && op->kind != TMF_P2_DIVKGRAD)
-    return fail(TMF_EUNSUPPORTED, "the diagonal is provided for the scalar P2 kinds");
+  if ((op->kind != TMF_P2_LAPLACE && op->kind != TMF_P2_DIVKGRAD) || op->nq > 0)
+    return fail(TMF_EUNSUPPORTED, "the diagonal is provided for the exactly integrated scalar P2 kinds");
   if (has_coeff(op->kind) != (coeff != nullptr))
     return fail(TMF_EINVAL, has_coeff(op->kind) ? "this operator needs a coefficient field"
                                                 : "this operator takes no coefficient field");
@@ -820,8 +824,8 @@ tmf_status tmf_diagonal(tmf_op *op, const void *coeff, void *d, tmf_stream strea
 
 tmf_status tmf_op_store_matrices(tmf_op *op, const void *coeff, tmf_stream stream) {
   if (!op || !coeff) return fail(TMF_EINVAL, "op or coeff is NULL");
-  if (op->kind != TMF_P2_DIVKGRAD)
-    return fail(TMF_EUNSUPPORTED, "stored local matrices are provided for TMF_P2_DIVKGRAD");
+  if (op->kind != TMF_P2_DIVKGRAD || op->nq > 0)
+    return fail(TMF_EUNSUPPORTED, "stored local matrices are provided for the exact TMF_P2_DIVKGRAD");
   const int cfg = op->tile_cfg;
   const size_t esz = op->prec == TMF_F64 ? 8 : 4;
   const size_t cubes = static_cast<size_t>(kTileCfg[cfg][0]) * kTileCfg[cfg][1] * kTileCfg[cfg][2];
@@ -950,6 +954,8 @@ tmf_status tmf_apply_adjoint(tmf_op *op, const void *coeff, const void *x, const
   if (!op) return fail(TMF_EINVAL, "op is NULL");
   if (op->kind != TMF_P1_DIVKGRAD && op->kind != TMF_P2_DIVKGRAD && op->kind != TMF_P2V_EPSILON)
     return fail(TMF_EUNSUPPORTED, "the adjoint is implemented for the div(k grad) and epsilon kinds");
+  if (op->kind == TMF_P2_DIVKGRAD && op->nq > 0)
+    return fail(TMF_EUNSUPPORTED, "the adjoint of the quadrature variant is not provided");
   if (!coeff || !x || !gy || !gx) return fail(TMF_EINVAL, "coeff, x, gy and gx are required");
   const void *ins[3] = {coeff, x, gy};
   for (const void *p : ins)

@@ -114,6 +114,61 @@ __device__ inline void grad_coeffs(const T u[10], T sp[4][3]) {
 //   y_edge bc  = 4 (sigma[c][b] + sigma[b][c])
 // (from grad phi_b = (4 lambda_b - 1) grad lambda_b and
 //  grad phi_bc = 4 (lambda_c grad lambda_b + lambda_b grad lambda_c)).
+// The apply with given coefficient weights W (see p2_elem).
+template <typename T>
+__device__ inline void p2_elem_w(const T u[10], const T W[4][4], CPtr<T> Gp, T y[10]) {
+  T sp[4][3];
+  grad_coeffs(u, sp);
+  T h[4][4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int d = 1; d < 4; ++d)
+      h[c][d] = sp[c][0] * Gp[4 * 1 + d] + sp[c][1] * Gp[4 * 2 + d] + sp[c][2] * Gp[4 * 3 + d];
+    h[c][0] = -(h[c][1] + h[c][2] + h[c][3]);
+  }
+  T sig[4][4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+      sig[e][d] = W[0][e] * h[0][d] + W[1][e] * h[1][d] + W[2][e] * h[2][d] + W[3][e] * h[3][d];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+    y[b] = T(4) * sig[b][b] - (sig[0][b] + sig[1][b] + sig[2][b] + sig[3][b]);
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int b = kEdge[e][0], c = kEdge[e][1];
+    y[4 + e] = T(4) * (sig[c][b] + sig[b][c]);
+  }
+}
+
+// Weights W_ce = (1/|T|) int k lambda_c lambda_e by a quadrature rule (the
+// under-integration variant): 6 sum_q w_q k(q) lambda_c(q) lambda_e(q), with
+// k(q) = sum_b k_b phi_b(q); table rows [w, lambda(4), phi(10), ...].
+template <typename T>
+__device__ inline void weights_quad(const T kv[10], CPtr<T> qtab, int nq, T W[4][4]) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) W[c][e] = T(0);
+  for (int q = 0; q < nq; ++q) {
+    CPtr<T> Q = qtab + q * kQStride;
+    T kq = T(0);
+#pragma unroll
+    for (int b = 0; b < 10; ++b) kq += kv[b] * Q[5 + b];
+    const T f = T(6) * Q[0] * kq;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int e = c; e < 4; ++e) W[c][e] += f * Q[1 + c] * Q[1 + e];
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int e = 0; e < c; ++e) W[c][e] = W[e][c];
+}
+
 template <typename T, bool HASK>
 __device__ inline void p2_elem(const T u[10], const T kv[10], CPtr<T> Gp, T y[10]) {
   T sp[4][3];
@@ -698,6 +753,17 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
     for (int v = 0; v < 10; ++v)
 #pragma unroll
       for (int c = 0; c < 3; ++c) atomicAdd(&sy[c][li[v]], double(y[c][v]));
+  } else if constexpr (KIND == P2_DIVKGRAD_Q) {
+    T u[10], kv[10], y[10], W[4][4];
+#pragma unroll
+    for (int v = 0; v < 10; ++v) {
+      u[v] = sx[0][li[v]];
+      kv[v] = sk[li[v]];
+    }
+    weights_quad(kv, cptr(a.qtab), a.nq, W);
+    p2_elem_w(u, W, cptr(g->Gp), y);
+#pragma unroll
+    for (int v = 0; v < 10; ++v) atomicAdd(&sy[0][li[v]], double(y[v]));
   } else if constexpr (KIND == P2_DIVKGRAD_STORE) {
     // columns A e_v of the local matrix; the upper triangle is stored
     T kv[10], A[10][10];
@@ -1203,6 +1269,7 @@ hipError_t launch_tile_apply(const TileArgs<T> &a, int kind, int map, int cfg, h
     case P2_DIVKGRAD: return launch_kind<T, P2_DIVKGRAD, 0>(a, cfg, s);
     case N1_CURLCURL: return launch_kind<T, N1_CURLCURL, 0>(a, cfg, s);
     case P2_DIVKGRAD_STORE: return launch_kind<T, P2_DIVKGRAD_STORE, 0>(a, cfg, s);
+    case P2_DIVKGRAD_Q: return launch_kind<T, P2_DIVKGRAD_Q, 0>(a, cfg, s);
     case P2_STORED_APPLY: return launch_kind<T, P2_STORED_APPLY, 0>(a, cfg, s);
     case P2_LAPLACE_DIAG: return launch_kind<T, P2_LAPLACE_DIAG, 0>(a, cfg, s);
     case P2_DIVKGRAD_DIAG: return launch_kind<T, P2_DIVKGRAD_DIAG, 0>(a, cfg, s);

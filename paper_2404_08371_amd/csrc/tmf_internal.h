@@ -93,7 +93,9 @@ enum KernelMode {
   // stored local matrices (the precomputed-matrix comparison): build them
   // from k, or apply them
   P2_DIVKGRAD_STORE = 20,
-  P2_STORED_APPLY = 21
+  P2_STORED_APPLY = 21,
+  // P2 div(k grad) with the weights from a quadrature rule (under-integration)
+  P2_DIVKGRAD_Q = 22
 };
 // entries of a stored symmetric 10 x 10 local matrix (upper triangle, row-major)
 constexpr int kStoredEntries = 55;
