@@ -42,18 +42,19 @@ PEAK_FP32 = 157.3e12    # FLOP/s, vector FP32
 # Arithmetic of each kernel's formulation, counted from the source (add, sub,
 # mul = 1 flop, fused multiply-add = 2), per unit the kernel processes.
 FLOPS = {
-    "p2_divkgrad": 358,        # per micro-tet: gradient coefficients, h, exact k-weights, sigma, outputs
+    "p2_divkgrad": 330,        # per micro-tet: gradient coefficients (40), exact k-weights (92), W^T sp (84),
+                               # sigma = (W^T sp) Gp (72), outputs (42)
     "p2_laplace": 184,         # per micro-tet: same without the coefficient weights
     "p1_laplace": 30,          # per DoF: 15-point stencil
     "p1_divkgrad": 312,        # per DoF: 24 incident micro-tets x (4x4 row, mean k, accumulate)
     "p1_adjoint": 1200,        # per DoF: forward row (312) + 24 x bilinear form (37)
-    "p2_adjoint": 946,         # per micro-tet: forward apply of gy (358) + coefficient gradient (588:
+    "p2_adjoint": 918,         # per micro-tet: forward apply of gy (330) + coefficient gradient (588:
                                # gradient coefficients 40, h 72, Gam 44, M 112, 10 x 16-term contractions 320)
     "eps_affine": 970,         # per micro-tet
     "n1": 440,                 # per micro-tet: 6 curls, curl u, curl part, U_p, B (beta weights), V, mass part
     "p2_stored": 200,          # per micro-tet: symmetric 10 x 10 matrix-vector product from 55 stored entries
     "p2_quad_per_q": 60,       # per micro-tet and quadrature point: k(q) (10 FMA) and 10 weight updates
-    "p2_no_weights": 266,      # per micro-tet: the P2 div(k grad) apply without its exact weights (358 - 92)
+    "p2_no_weights": 266,      # per micro-tet: the quadrature-variant apply without its weights (h = sp Gp form)
     "eps_blended_per_q": 657,  # per micro-tet and quadrature point (map Jacobian, inverse, 2 x 90-term contractions)
     "eps_blended_adjoint_per_q": 1337,  # forward of gy (657) + mu gradient (680: map Jacobian and inverse,
                                         # gradients of x and gy, strain contraction, 10-node scatter)

@@ -173,24 +173,31 @@ template <typename T, bool HASK>
 __device__ inline void p2_elem(const T u[10], const T kv[10], CPtr<T> Gp, T y[10]) {
   T sp[4][3];
   grad_coeffs(u, sp);
-  T h[4][4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-#pragma unroll
-    for (int d = 1; d < 4; ++d)
-      h[c][d] = sp[c][0] * Gp[4 * 1 + d] + sp[c][1] * Gp[4 * 2 + d] + sp[c][2] * Gp[4 * 3 + d];
-    h[c][0] = -(h[c][1] + h[c][2] + h[c][3]);
-  }
   T sig[4][4];
   if (HASK) {
+    // sig = W^T h with h = sp Gp, evaluated as (W^T sp) Gp: 4 x 3 then 4 x 3
+    // products instead of 4 x 3 then 4 x 4 (Gp has zero row sums, so the
+    // column of lambda_0 follows from the other three)
     T W[4][4];
     weights_p2(kv, W);
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
+    for (int e = 0; e < 4; ++e) {
+      T Q[3];
 #pragma unroll
-      for (int d = 0; d < 4; ++d)
-        sig[e][d] = W[0][e] * h[0][d] + W[1][e] * h[1][d] + W[2][e] * h[2][d] + W[3][e] * h[3][d];
+      for (int a = 0; a < 3; ++a) Q[a] = W[0][e] * sp[0][a] + W[1][e] * sp[1][a] + W[2][e] * sp[2][a] + W[3][e] * sp[3][a];
+#pragma unroll
+      for (int d = 1; d < 4; ++d) sig[e][d] = Q[0] * Gp[4 * 1 + d] + Q[1] * Gp[4 * 2 + d] + Q[2] * Gp[4 * 3 + d];
+      sig[e][0] = -(sig[e][1] + sig[e][2] + sig[e][3]);
+    }
   } else {
+    T h[4][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+      for (int d = 1; d < 4; ++d)
+        h[c][d] = sp[c][0] * Gp[4 * 1 + d] + sp[c][1] * Gp[4 * 2 + d] + sp[c][2] * Gp[4 * 3 + d];
+      h[c][0] = -(h[c][1] + h[c][2] + h[c][3]);
+    }
     // W = (1 + delta)/20
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
