@@ -42,13 +42,13 @@ PEAK_FP32 = 157.3e12    # FLOP/s, vector FP32
 # Arithmetic of each kernel's formulation, counted from the source (add, sub,
 # mul = 1 flop, fused multiply-add = 2), per unit the kernel processes.
 FLOPS = {
-    "p2_divkgrad": 330,        # per micro-tet: gradient coefficients (40), exact k-weights (92), W^T sp (84),
-                               # sigma = (W^T sp) Gp (72), outputs (42)
+    "p2_divkgrad": 276,        # per micro-tet: gradient coefficients (40), exact k-weights x 840 (58),
+                               # W^T sp (84), sigma = (W^T sp) Gs (68), outputs (26)
     "p2_laplace": 184,         # per micro-tet: same without the coefficient weights
     "p1_laplace": 30,          # per DoF: 15-point stencil
     "p1_divkgrad": 312,        # per DoF: 24 incident micro-tets x (4x4 row, mean k, accumulate)
     "p1_adjoint": 1200,        # per DoF: forward row (312) + 24 x bilinear form (37)
-    "p2_adjoint": 918,         # per micro-tet: forward apply of gy (330) + coefficient gradient (588:
+    "p2_adjoint": 864,         # per micro-tet: forward apply of gy (276) + coefficient gradient (588:
                                # gradient coefficients 40, h 72, Gam 44, M 112, 10 x 16-term contractions 320)
     "eps_affine": 970,         # per micro-tet
     "n1": 440,                 # per micro-tet: 6 curls, curl u, curl part, U_p, B (beta weights), V, mass part

@@ -342,6 +342,7 @@ void fill_geometry(const tmf_mesh *m, std::vector<TypeGeo<T>> &geo, std::vector<
         for (int b = 0; b < 4; ++b) {
           const double v = vol * (gr[a][0] * gr[b][0] + gr[a][1] * gr[b][1] + gr[a][2] * gr[b][2]);
           tg.Gp[4 * a + b] = T(v);
+          if (a > 0) tg.Gs[4 * (a - 1) + b] = T(v / 210.0);
         }
       for (int a = 0; a < 4; ++a)
         for (int d = 0; d < 3; ++d) tg.grad[3 * a + d] = T(gr[a][d]);

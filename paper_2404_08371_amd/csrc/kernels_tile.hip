@@ -86,6 +86,36 @@ __device__ inline void weights_p2(const T kv[10], T W[4][4]) {
   }
 }
 
+// The same weights scaled by 840, with the Bernstein sums collected in the
+// nodal values: with V = sum of the vertex values k_c, E_c = sum of the edge
+// values at vertex c and h = sum_c E_c - 3 V / 2,
+//   840 W_ce = 4 k_ce + b_c + b_e  (c != e),   840 W_cc = 4 (b_c + 2 k_c),
+//   b_c = k_c + 4 E_c + h
+// (43 operations instead of 71 for the form above).
+template <typename T>
+__device__ inline void weights_p2_840(const T kv[10], T W[4][4]) {
+  T E[4];
+  E[0] = kv[4] + kv[5] + kv[6];
+  E[1] = kv[4] + kv[7] + kv[8];
+  E[2] = kv[5] + kv[7] + kv[9];
+  E[3] = kv[6] + kv[8] + kv[9];
+  const T V = (kv[0] + kv[1]) + (kv[2] + kv[3]);
+  const T h = T(-1.5) * V + ((E[0] + E[1]) + (E[2] + E[3]));
+  T b[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    b[c] = T(4) * E[c] + (kv[c] + h);
+    W[c][c] = T(4) * (T(2) * kv[c] + b[c]);
+  }
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int c = kEdge[e][0], d = kEdge[e][1];
+    const T v = T(4) * kv[4 + e] + (b[c] + b[d]);
+    W[c][d] = v;
+    W[d][c] = v;
+  }
+}
+
 // Gradient coefficients of a P2 field on an affine tet in the barycentric
 // gradient basis: grad u = sum_c lambda_c g_c with g_c = sum_a s[c][a] grad(lambda_a),
 // s[c][c] = 3 u_c, s[c][a] = 4 u_ca - u_a.  Returned shifted by s[c][0]
@@ -170,24 +200,33 @@ __device__ inline void weights_quad(const T kv[10], CPtr<T> qtab, int nq, T W[4]
 }
 
 template <typename T, bool HASK>
-__device__ inline void p2_elem(const T u[10], const T kv[10], CPtr<T> Gp, T y[10]) {
+__device__ inline void p2_elem(const T u[10], const T kv[10], CPtr<T> Gp, CPtr<T> Gs, T y[10]) {
   T sp[4][3];
   grad_coeffs(u, sp);
-  T sig[4][4];
   if (HASK) {
-    // sig = W^T h with h = sp Gp, evaluated as (W^T sp) Gp: 4 x 3 then 4 x 3
-    // products instead of 4 x 3 then 4 x 4 (Gp has zero row sums, so the
-    // column of lambda_0 follows from the other three)
+    // sig' = 4 sig = (W'^T sp) Gs with W' = 840 W and Gs = Gp / 210 (rows
+    // 1..3; Gp has zero row sums, so the column of lambda_0 follows from the
+    // other three): 4 x 3 then 4 x 3 products, and the edge outputs become
+    // plain sums
     T W[4][4];
-    weights_p2(kv, W);
+    weights_p2_840(kv, W);
+    T sig[4][4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       T Q[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) Q[a] = W[0][e] * sp[0][a] + W[1][e] * sp[1][a] + W[2][e] * sp[2][a] + W[3][e] * sp[3][a];
 #pragma unroll
-      for (int d = 1; d < 4; ++d) sig[e][d] = Q[0] * Gp[4 * 1 + d] + Q[1] * Gp[4 * 2 + d] + Q[2] * Gp[4 * 3 + d];
+      for (int d = 1; d < 4; ++d) sig[e][d] = Q[0] * Gs[d] + Q[1] * Gs[4 + d] + Q[2] * Gs[8 + d];
       sig[e][0] = -(sig[e][1] + sig[e][2] + sig[e][3]);
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      y[b] = sig[b][b] - T(0.25) * (sig[0][b] + sig[1][b] + sig[2][b] + sig[3][b]);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      const int b = kEdge[e][0], c = kEdge[e][1];
+      y[4 + e] = sig[c][b] + sig[b][c];
     }
   } else {
     T h[4][4];
@@ -199,20 +238,21 @@ __device__ inline void p2_elem(const T u[10], const T kv[10], CPtr<T> Gp, T y[10
       h[c][0] = -(h[c][1] + h[c][2] + h[c][3]);
     }
     // W = (1 + delta)/20
+    T sig[4][4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
       const T H = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 #pragma unroll
       for (int e = 0; e < 4; ++e) sig[e][d] = (H + h[e][d]) * T(0.05);
     }
-  }
 #pragma unroll
-  for (int b = 0; b < 4; ++b)
-    y[b] = T(4) * sig[b][b] - (sig[0][b] + sig[1][b] + sig[2][b] + sig[3][b]);
+    for (int b = 0; b < 4; ++b)
+      y[b] = T(4) * sig[b][b] - (sig[0][b] + sig[1][b] + sig[2][b] + sig[3][b]);
 #pragma unroll
-  for (int e = 0; e < 6; ++e) {
-    const int b = kEdge[e][0], c = kEdge[e][1];
-    y[4 + e] = T(4) * (sig[c][b] + sig[b][c]);
+    for (int e = 0; e < 6; ++e) {
+      const int b = kEdge[e][0], c = kEdge[e][1];
+      y[4 + e] = T(4) * (sig[c][b] + sig[b][c]);
+    }
   }
 }
 
@@ -220,13 +260,13 @@ __device__ inline void p2_elem(const T u[10], const T kv[10], CPtr<T> Gp, T y[10
 // are compile-time constants, so the unrolled calls fold to the terms that
 // touch node v (and the coefficient weights are formed once).
 template <typename T, bool HASK>
-__device__ inline void p2_diag(const T kv[10], CPtr<T> Gp, T d[10]) {
+__device__ inline void p2_diag(const T kv[10], CPtr<T> Gp, CPtr<T> Gs, T d[10]) {
 #pragma unroll
   for (int v = 0; v < 10; ++v) {
     T u[10], y[10];
 #pragma unroll
     for (int w = 0; w < 10; ++w) u[w] = w == v ? T(1) : T(0);
-    p2_elem<T, HASK>(u, kv, Gp, y);
+    p2_elem<T, HASK>(u, kv, Gp, Gs, y);
     d[v] = y[v];
   }
 }
@@ -781,7 +821,7 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
       T u[10];
 #pragma unroll
       for (int w = 0; w < 10; ++w) u[w] = w == v ? T(1) : T(0);
-      p2_elem<T, true>(u, kv, cptr(g->Gp), A[v]);
+      p2_elem<T, true>(u, kv, cptr(g->Gp), cptr(g->Gs), A[v]);
     }
     int e = 0;
 #pragma unroll
@@ -858,7 +898,7 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
     T kv[10], d[10];
 #pragma unroll
     for (int v = 0; v < 10; ++v) kv[v] = HASK ? sk[li[v]] : T(1);
-    p2_diag<T, HASK>(kv, cptr(g->Gp), d);
+    p2_diag<T, HASK>(kv, cptr(g->Gp), cptr(g->Gs), d);
 #pragma unroll
     for (int v = 0; v < 10; ++v) atomicAdd(&sy[0][li[v]], double(d[v]));
   } else {
@@ -869,7 +909,7 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
       u[v] = sx[0][li[v]];
       kv[v] = HASK ? sk[li[v]] : T(1);
     }
-    p2_elem<T, HASK>(u, kv, cptr(g->Gp), y);
+    p2_elem<T, HASK>(u, kv, cptr(g->Gp), cptr(g->Gs), y);
 #pragma unroll
     for (int v = 0; v < 10; ++v) atomicAdd(&sy[0][li[v]], double(y[v]));
   }

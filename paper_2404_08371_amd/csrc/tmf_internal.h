@@ -50,12 +50,15 @@ constexpr int vslot(int t, int a, int c) {
 //   Gp[a][b] = |T| grad(lambda_a) . grad(lambda_b)   (P1 local matrix)
 //   grad[a][d] = grad(lambda_a), vol = |T|
 //   JT = parametric Jacobian of the micro-tet (columns: edge vectors from vertex 0)
+//   Gs = rows 1..3 of Gp / 210 (the P2 div(k grad) element forms its weights
+//        scaled by 840 and its sigma scaled by 4, so 4 / 840 is folded in here)
 template <typename T>
 struct TypeGeo {
   T Gp[16];
   T grad[12];
   T vol;
   T JT[9];
+  T Gs[12];
   T pad[2];
 };
 
