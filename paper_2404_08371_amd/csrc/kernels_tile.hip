@@ -42,6 +42,21 @@ template <typename T>
 __device__ __forceinline__ CPtr<T> cptr(const T *p) {
   return (CPtr<T>)p;
 }
+// A pointer read from a descriptor in memory has no known address space, so
+// accesses through it compile to flat instructions, which count against both
+// the vector-memory and the LDS wait counters: a later LDS wait then also
+// waits for every flat load or store in flight, and loads that the code
+// issues one after another complete one after another.  Per-lane accesses
+// through such pointers are therefore cast to the global address space.
+template <typename T>
+using GPtr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ GPtr<T> gptr(T *p) {
+  return (GPtr<T>)p;
+}
+// LDS view of a __shared__ array (a generic pointer to it would again be flat)
+template <typename T>
+using LPtr = const __attribute__((address_space(3))) T *;
 
 // Exact weights W_ce = (1/|T|) int_T k lambda_c lambda_e for k nodal P2.
 // k in Bernstein form: k = sum_b kappa_b B_b, B_aa = lambda_a^2,
@@ -771,7 +786,7 @@ struct TileCfg {
 template <typename T, int KIND, int MAP, int R, int t, int CS>
 __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T> *D, T (*sx)[R], const T *sk,
                                           double (*sy)[R], const int li[10], int m, int bxc, int byc, int bzc,
-                                          T *me) {
+                                          GPtr<T> me) {
   const TypeGeo<T> *g = D->geo + 6 * m + t;
   if constexpr (KIND == P2V_EPSILON) {
     T u[3][10], mu[10], y[3][10];
@@ -942,7 +957,7 @@ __device__ __forceinline__ void cube_elem(const TileArgs<T> &a, const InstDesc<T
 #pragma unroll
   for (int v = 0; v < 10; ++v) li[v] = cb + node_off(t, v, RY, OO, RXP);
   // stored-matrix modes: the element's 55 entries at me[e * C], e = 0..54
-  T *me = Cfg::STORED ? a.mat + (static_cast<int64_t>(tw) * 6 + t) * kStoredEntries * Cfg::C + c : nullptr;
+  GPtr<T> me = gptr(Cfg::STORED ? a.mat + (static_cast<int64_t>(tw) * 6 + t) * kStoredEntries * Cfg::C + c : a.mat);
   tile_elem<T, KIND, MAP, R, t, Cfg::C>(a, D, sx, sk, sy, li, m, bx0 + cx, by0 + cy, bz0 + cz, me);
 }
 
@@ -985,7 +1000,7 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
   const int bx0 = tl.z & 1023, by0 = (tl.z >> 10) & 1023, bz0 = (tl.z >> 20) & 1023;
   const int N = D->N;
   const int64_t nl = D->n_local;
-  const uint32_t bnd = D->dirichlet ? D->bnd[m] : 0u;
+  const uint32_t bnd = D->dirichlet ? *cptr(D->bnd + m) : 0u;
   const int64_t base = D->off + static_cast<int64_t>(m) * D->L;
 
   // 0. the box's lattice rows (qj, qk): start offset in the macro block, and
@@ -1037,7 +1052,7 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
         }
         if constexpr (Cfg::N1) {
           // x in the lattice orientation; alpha and beta live at the vertex points
-          sgv[p] = D->sign[base + off];
+          sgv[p] = gptr(D->sign)[base + off];
           xv[p][0] *= T(sgv[p]);
           const int ry = row % RY, rz = row / RY;
           if (!(rx & 1) && !(ry & 1) && !(rz & 1)) {
@@ -1100,7 +1115,7 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
 
   // 3. write back: points of this box alone go to y (Dirichlet DoFs as 0),
   // points of shared box faces to this tile's partials [component][box point]
-  T *pt = D->partial + static_cast<int64_t>(tl.w) * NC * R;
+  GPtr<T> pt = gptr(D->partial) + static_cast<int64_t>(tl.w) * NC * R;
   for (int r = tid; r < R; r += NTH) {
     const int row = r / RX, rx = r - row * RX;
     const int info = sri[row], lim = info >> 8, qi = 2 * bx0 + rx;
@@ -1136,9 +1151,8 @@ __device__ __forceinline__ bool is_seam(int qx, int qy, int qz) {
   return (qx > 0 && qx % (2 * TX) == 0) || (qy > 0 && qy % (2 * TY) == 0) || (qz > 0 && qz % (2 * TZ) == 0);
 }
 
-template <typename T, int NC, int TX, int TY, int TZ>
-__device__ __forceinline__ void seam_sum(const SeamInst<T> &a, const int *rs, int m, int qx, int qy, int qz,
-                                         T acc[NC]) {
+template <typename T, int NC, int TX, int TY, int TZ, typename RS>
+__device__ __forceinline__ void seam_sum(const SeamInst<T> &a, RS rs, int m, int qx, int qy, int qz, T acc[NC]) {
   constexpr int RX = 2 * TX + 1, RY = 2 * TY + 1, R = RX * RY * (2 * TZ + 1);
   auto lower = [](int q, int t) { return (q > 0 && q % (2 * t) == 0) ? q / 2 - t : t * (q / (2 * t)); };
   const int x0 = lower(qx, TX), y0 = lower(qy, TY), z0 = lower(qz, TZ);
@@ -1162,7 +1176,7 @@ __device__ __forceinline__ void seam_sum(const SeamInst<T> &a, const int *rs, in
         const int r = (qx - 2 * bx) + RX * ((qy - 2 * by) + RY * (qz - 2 * bz));
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          const T val = a.partial[ok ? (tile * NC + c) * R + r : 0];
+          const T val = gptr(a.partial)[ok ? (tile * NC + c) * R + r : 0];
           v[e][c] = ok ? val : T(0);
         }
       }
@@ -1203,16 +1217,16 @@ __global__ __launch_bounds__(256) void k_seam(const SeamInst<T> *__restrict__ in
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
       const int p = w.z + t + 256 * u;
-      pks[u] = p < a.npts ? a.pts[p] : -1;
+      pks[u] = p < a.npts ? gptr(a.pts)[p] : -1;
     }
   } else {
     const int q = w.y + t;
     mine = q < w.z;
     pks[0] = 0;
     if (mine) {
-      const int64_t pos = a.gpos[q];
-      slot = a.gidx[q];
-      pl = a.gpl[q];
+      const int64_t pos = gptr(a.gpos)[q];
+      slot = gptr(a.gidx)[q];
+      pl = gptr(a.gpl)[q];
       m = static_cast<int>(pos >> 32);
       pks[0] = static_cast<int>(pos & 0xffffffff);
     }
@@ -1220,72 +1234,78 @@ __global__ __launch_bounds__(256) void k_seam(const SeamInst<T> *__restrict__ in
   const int nrows = ((a.n + TZ - 1) / TZ) * a.nby;
   const bool in_lds = nrows <= rows_lds;
   if (in_lds)
-    for (int e = t; e < nrows; e += 256) srs[e] = a.rowstart[e];
+    for (int e = t; e < nrows; e += 256) srs[e] = gptr(a.rowstart)[e];
   __syncthreads();
-  const int *rs = in_lds ? srs : a.rowstart;
   T *yi = y + a.yoff;
-  if (!grp) {
-    // seam points of macro m (PPT per thread, 256 apart); points with copies
-    // in other macros are left to their interface group (unless a
-    // macro-local result is asked for)
-    // every point's loads first, then the stores (the compiler cannot move a
-    // load of one point above the store of another: y and the partials may alias)
-    const uint32_t bm = a.dirichlet && !(flags & kSeamKeepBoundary) ? a.bnd[m] : 0u;
-    const uint32_t sh = local ? 0u : a.shared[m];
-    T acc[PPT][NC];
-    int64_t sl[PPT];
-    bool wr[PPT], dz[PPT];
+  // the rest once with the row table in LDS, once reading it from global memory
+  auto body = [&](auto rs) {
+    if (!grp) {
+      // seam points of macro m (PPT per thread, 256 apart); points with copies
+      // in other macros are left to their interface group (unless a
+      // macro-local result is asked for)
+      // every point's loads first, then the stores (the compiler cannot move a
+      // load of one point above the store of another: y and the partials may alias)
+      const uint32_t bm = a.dirichlet && !(flags & kSeamKeepBoundary) ? *cptr(a.bnd + m) : 0u;
+      const uint32_t sh = local ? 0u : *cptr(a.shared + m);
+      T acc[PPT][NC];
+      int64_t sl[PPT];
+      bool wr[PPT], dz[PPT];
 #pragma unroll
-    for (int u = 0; u < PPT; ++u) {
-      const int pk = pks[u] < 0 ? 0 : pks[u];
-      const int qx = pk & 1023, qy = (pk >> 10) & 1023, qz = pk >> 20;
-      const int z = zero_pattern(qx, qy, qz, a.N);
-      wr[u] = pks[u] >= 0 && !((sh >> z) & 1u);
-      dz[u] = (bm >> z) & 1u;
-      sl[u] = static_cast<int64_t>(m) * a.L + row_base(qy, qz, a.N) + qx;
-      seam_sum<T, NC, TX, TY, TZ>(a, rs, m, qx, qy, qz, acc[u]);
+      for (int u = 0; u < PPT; ++u) {
+        const int pk = pks[u] < 0 ? 0 : pks[u];
+        const int qx = pk & 1023, qy = (pk >> 10) & 1023, qz = pk >> 20;
+        const int z = zero_pattern(qx, qy, qz, a.N);
+        wr[u] = pks[u] >= 0 && !((sh >> z) & 1u);
+        dz[u] = (bm >> z) & 1u;
+        sl[u] = static_cast<int64_t>(m) * a.L + row_base(qy, qz, a.N) + qx;
+        seam_sum<T, NC, TX, TY, TZ>(a, rs, m, qx, qy, qz, acc[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < PPT; ++u)
+        if (wr[u])
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+            __builtin_nontemporal_store(dz[u] ? T(0) : acc[u][c], &yi[sl[u] + c * a.n_local]);
+      return;
+    }
+    const int pk = pks[0];
+    const int qx = pk & 1023, qy = (pk >> 10) & 1023, qz = pk >> 20;
+    const int z = zero_pattern(qx, qy, qz, a.N);
+    const bool dir = a.dirichlet && !(flags & kSeamKeepBoundary) && ((gptr(a.bnd)[m] >> z) & 1u);
+    // interface groups: each member's macro-local value (seam sum or the tile
+    // kernel's store) goes to LDS; every member then adds its group's values in
+    // ascending member order, so all copies receive the same sum
+    if (mine) {
+      T v[NC];
+      if (is_seam<TX, TY, TZ>(qx, qy, qz)) {
+        seam_sum<T, NC, TX, TY, TZ>(a, rs, m, qx, qy, qz, v);
+      } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = yi[slot + c * a.n_local];
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) sv[c][t] = v[c];
+      sd[t] = dir;
+    }
+    __syncthreads();
+    if (!mine) return;
+    const int len = pl & 0xffff, h = t - (pl >> 16);
+    T sum[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) sum[c] = T(0);
+    bool gdir = false;
+    for (int i = h; i < h + len; ++i) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) sum[c] += sv[c][i];
+      gdir = gdir || sd[i];
     }
 #pragma unroll
-    for (int u = 0; u < PPT; ++u)
-      if (wr[u])
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-          __builtin_nontemporal_store(dz[u] ? T(0) : acc[u][c], &yi[sl[u] + c * a.n_local]);
-    return;
-  }
-  const int pk = pks[0];
-  const int qx = pk & 1023, qy = (pk >> 10) & 1023, qz = pk >> 20;
-  const int z = zero_pattern(qx, qy, qz, a.N);
-  const bool dir = a.dirichlet && !(flags & kSeamKeepBoundary) && ((a.bnd[m] >> z) & 1u);
-  // interface groups: each member's macro-local value (seam sum or the tile
-  // kernel's store) goes to LDS; every member then adds its group's values in
-  // ascending member order, so all copies receive the same sum
-  if (mine) {
-    T v[NC];
-    if (is_seam<TX, TY, TZ>(qx, qy, qz)) {
-      seam_sum<T, NC, TX, TY, TZ>(a, rs, m, qx, qy, qz, v);
-    } else {
-#pragma unroll
-      for (int c = 0; c < NC; ++c) v[c] = yi[slot + c * a.n_local];
-    }
-#pragma unroll
-    for (int c = 0; c < NC; ++c) sv[c][t] = v[c];
-    sd[t] = dir;
-  }
-  __syncthreads();
-  if (!mine) return;
-  const int len = pl & 0xffff, h = t - (pl >> 16);
-  T sum[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) sum[c] = T(0);
-  bool gdir = false;
-  for (int i = h; i < h + len; ++i) {
-#pragma unroll
-    for (int c = 0; c < NC; ++c) sum[c] += sv[c][i];
-    gdir = gdir || sd[i];
-  }
-#pragma unroll
-  for (int c = 0; c < NC; ++c) __builtin_nontemporal_store(gdir ? T(0) : sum[c], &yi[slot + c * a.n_local]);
+    for (int c = 0; c < NC; ++c) __builtin_nontemporal_store(gdir ? T(0) : sum[c], &yi[slot + c * a.n_local]);
+  };
+  if (in_lds)
+    body((LPtr<int>)srs);
+  else
+    body(gptr(a.rowstart));
 }
 
 template <typename T, int KIND, int MAP, int TX, int TY, int TZ>
