@@ -153,10 +153,23 @@ def kernel_mean_ms(hip, evs, stats=None):
 
 
 def clock_state():
-    """Current GPU clocks as rocm-smi reports them (None when it is not available)."""
+    """Current GPU clocks as rocm-smi reports them (None when it is not available).
+
+    rocm-smi is a Python script: it is run by this interpreter directly, since
+    its `env` shebang would replace a process by another one.  Under a profiler
+    (a preloaded tool library, which would also load into the child) no clocks
+    are read."""
+    import shutil
     import subprocess
+    env = os.environ
+    if ("rocprof" in env.get("LD_PRELOAD", "") + env.get("HSA_TOOLS_LIB", "")
+            or any(k.startswith("ROCPROF") for k in env)):
+        return None
+    smi = shutil.which("rocm-smi")
+    if smi is None:
+        return None
     try:
-        r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=20)
+        r = subprocess.run([sys.executable, smi, "--showclocks"], capture_output=True, text=True, timeout=20)
     except (OSError, subprocess.SubprocessError):
         return None
     lines = [ln.strip() for ln in r.stdout.splitlines() if "clock level" in ln.lower() or "Mhz" in ln]
