@@ -1159,27 +1159,33 @@ __device__ __forceinline__ void seam_sum(const SeamInst<T> &a, RS rs, int m, int
   const int nx = (qx > 0 && qx % (2 * TX) == 0) ? 2 : 1;
   const int ny = (qy > 0 && qy % (2 * TY) == 0) ? 2 : 1;
   const int nz = (qz > 0 && qz % (2 * TZ) == 0) ? 2 : 1;
-  // all 8 candidates without branches, so their loads are in flight together:
-  // a candidate that does not exist reads entry 0 of the buffer and adds +0,
-  // which leaves the sum (started at +0) unchanged
+  // a candidate's loads are issued only where it exists (a wavefront of face
+  // points skips the candidates across the other two faces), and none of the
+  // loads is used before all are issued, so they are in flight together; a
+  // missing candidate adds +0, which leaves the sum (started at +0) unchanged.
+  // The tile-row lookups come first, for every candidate (entry 0 where it
+  // does not exist), so they too are in flight together.
+  int64_t tile[8];
+  int rr[8];
+  bool ok[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int ix = e & 1, iy = (e >> 1) & 1, iz = e >> 2;
+    const int bx = x0 + ix * TX, by = y0 + iy * TY, bz = z0 + iz * TZ;
+    ok[e] = ix < nx && iy < ny && iz < nz && bx + by + bz <= a.n - 1;
+    tile[e] = static_cast<int64_t>(m) * a.tpm + rs[ok[e] ? (bz / TZ) * a.nby + by / TY : 0] + bx / TX;
+    rr[e] = (qx - 2 * bx) + RX * ((qy - 2 * by) + RY * (qz - 2 * bz));
+  }
   T v[8][NC];
 #pragma unroll
-  for (int iz = 0; iz < 2; ++iz)
+  for (int e = 0; e < 8; ++e) {
 #pragma unroll
-    for (int iy = 0; iy < 2; ++iy)
+    for (int c = 0; c < NC; ++c) v[e][c] = T(0);
+    if (ok[e]) {
 #pragma unroll
-      for (int ix = 0; ix < 2; ++ix) {
-        const int bx = x0 + ix * TX, by = y0 + iy * TY, bz = z0 + iz * TZ;
-        const bool ok = ix < nx && iy < ny && iz < nz && bx + by + bz <= a.n - 1;
-        const int e = 4 * iz + 2 * iy + ix;
-        const int64_t tile = static_cast<int64_t>(m) * a.tpm + rs[ok ? (bz / TZ) * a.nby + by / TY : 0] + bx / TX;
-        const int r = (qx - 2 * bx) + RX * ((qy - 2 * by) + RY * (qz - 2 * bz));
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const T val = gptr(a.partial)[ok ? (tile * NC + c) * R + r : 0];
-          v[e][c] = ok ? val : T(0);
-        }
-      }
+      for (int c = 0; c < NC; ++c) v[e][c] = gptr(a.partial)[(tile[e] * NC + c) * R + rr[e]];
+    }
+  }
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     T s = T(0);
