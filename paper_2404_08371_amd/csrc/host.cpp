@@ -567,7 +567,11 @@ tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const
       op->nseam[cfg] = static_cast<int>(pts.size());
       if (st == TMF_OK) st = op->seam[cfg].upload(pts.data(), pts.size());
       const size_t R = static_cast<size_t>(2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1);
-      partial_bytes = std::max(partial_bytes, tl.size() * R * op->ncomp * (prec == TMF_F64 ? 8 : 4));
+      const size_t per_tile = R * op->ncomp * (prec == TMF_F64 ? 8 : 4);
+      partial_bytes = std::max(partial_bytes, tl.size() * per_tile);
+      // the gather addresses one macro's partial sums by 32-bit byte offsets
+      if (st == TMF_OK && (tl.size() / static_cast<size_t>(mesh->nt)) * per_tile > 0xffffffffull)
+        st = fail(TMF_EINVAL, "partial sums of one macro exceed 4 GiB at this level");
     }
     if (st == TMF_OK) st = op->partial.alloc(partial_bytes);
     // interface-group members as (macro, lattice point), and per macro the

@@ -1151,8 +1151,18 @@ __device__ __forceinline__ bool is_seam(int qx, int qy, int qz) {
   return (qx > 0 && qx % (2 * TX) == 0) || (qy > 0 && qy % (2 * TY) == 0) || (qz > 0 && qz % (2 * TZ) == 0);
 }
 
+// Macro m's partial sums form one block of tpm NC R values, below 10^9 bytes
+// at the largest level, so a candidate is addressed by the block's 64-bit base
+// (uniform over a seam work entry) and a 32-bit byte offset.
+template <typename T, int NC, int TX, int TY, int TZ>
+__device__ __forceinline__ GPtr<const char> partial_block(const SeamInst<T> &a, int m) {
+  constexpr int R = (2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1);
+  return (GPtr<const char>)gptr(a.partial + static_cast<int64_t>(m) * a.tpm * NC * R);
+}
+
 template <typename T, int NC, int TX, int TY, int TZ, typename RS>
-__device__ __forceinline__ void seam_sum(const SeamInst<T> &a, RS rs, int m, int qx, int qy, int qz, T acc[NC]) {
+__device__ __forceinline__ void seam_sum(const SeamInst<T> &a, RS rs, GPtr<const char> pm, int qx, int qy, int qz,
+                                         T acc[NC]) {
   constexpr int RX = 2 * TX + 1, RY = 2 * TY + 1, R = RX * RY * (2 * TZ + 1);
   auto lower = [](int q, int t) { return (q > 0 && q % (2 * t) == 0) ? q / 2 - t : t * (q / (2 * t)); };
   const int x0 = lower(qx, TX), y0 = lower(qy, TY), z0 = lower(qz, TZ);
@@ -1165,16 +1175,16 @@ __device__ __forceinline__ void seam_sum(const SeamInst<T> &a, RS rs, int m, int
   // missing candidate adds +0, which leaves the sum (started at +0) unchanged.
   // The tile-row lookups come first, for every candidate (entry 0 where it
   // does not exist), so they too are in flight together.
-  int64_t tile[8];
-  int rr[8];
+  uint32_t boff[8];
   bool ok[8];
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const int ix = e & 1, iy = (e >> 1) & 1, iz = e >> 2;
     const int bx = x0 + ix * TX, by = y0 + iy * TY, bz = z0 + iz * TZ;
     ok[e] = ix < nx && iy < ny && iz < nz && bx + by + bz <= a.n - 1;
-    tile[e] = static_cast<int64_t>(m) * a.tpm + rs[ok[e] ? (bz / TZ) * a.nby + by / TY : 0] + bx / TX;
-    rr[e] = (qx - 2 * bx) + RX * ((qy - 2 * by) + RY * (qz - 2 * bz));
+    const uint32_t tile = static_cast<uint32_t>(rs[ok[e] ? (bz / TZ) * a.nby + by / TY : 0] + bx / TX);
+    const uint32_t r = static_cast<uint32_t>((qx - 2 * bx) + RX * ((qy - 2 * by) + RY * (qz - 2 * bz)));
+    boff[e] = (tile * (NC * R) + r) * static_cast<uint32_t>(sizeof(T));
   }
   T v[8][NC];
 #pragma unroll
@@ -1183,7 +1193,8 @@ __device__ __forceinline__ void seam_sum(const SeamInst<T> &a, RS rs, int m, int
     for (int c = 0; c < NC; ++c) v[e][c] = T(0);
     if (ok[e]) {
 #pragma unroll
-      for (int c = 0; c < NC; ++c) v[e][c] = gptr(a.partial)[(tile[e] * NC + c) * R + rr[e]];
+      for (int c = 0; c < NC; ++c)
+        v[e][c] = *(GPtr<const T>)(pm + (boff[e] + static_cast<uint32_t>(c * R * sizeof(T))));
     }
   }
 #pragma unroll
@@ -1201,7 +1212,7 @@ __device__ __forceinline__ void seam_sum(const SeamInst<T> &a, RS rs, int m, int
 // starts of the instance are staged in dynamic LDS (`rows_lds` entries; a
 // larger table is read from global memory).
 template <typename T, int NC, int PPT, int TX, int TY, int TZ>
-__global__ __launch_bounds__(256) void k_seam(const SeamInst<T> *__restrict__ insts, const int4 *__restrict__ work,
+__global__ __launch_bounds__(256, 5) void k_seam(const SeamInst<T> *__restrict__ insts, const int4 *__restrict__ work,
                                               T *__restrict__ y, const uint8_t *__restrict__ active, int flags,
                                               int rows_lds) {
   const bool local = flags & kSeamLocal;
@@ -1253,6 +1264,7 @@ __global__ __launch_bounds__(256) void k_seam(const SeamInst<T> *__restrict__ in
       // load of one point above the store of another: y and the partials may alias)
       const uint32_t bm = a.dirichlet && !(flags & kSeamKeepBoundary) ? *cptr(a.bnd + m) : 0u;
       const uint32_t sh = local ? 0u : *cptr(a.shared + m);
+      const GPtr<const char> pmw = partial_block<T, NC, TX, TY, TZ>(a, w.y);
       T acc[PPT][NC];
       int64_t sl[PPT];
       bool wr[PPT], dz[PPT];
@@ -1264,7 +1276,7 @@ __global__ __launch_bounds__(256) void k_seam(const SeamInst<T> *__restrict__ in
         wr[u] = pks[u] >= 0 && !((sh >> z) & 1u);
         dz[u] = (bm >> z) & 1u;
         sl[u] = static_cast<int64_t>(m) * a.L + row_base(qy, qz, a.N) + qx;
-        seam_sum<T, NC, TX, TY, TZ>(a, rs, m, qx, qy, qz, acc[u]);
+        seam_sum<T, NC, TX, TY, TZ>(a, rs, pmw, qx, qy, qz, acc[u]);
       }
 #pragma unroll
       for (int u = 0; u < PPT; ++u)
@@ -1284,7 +1296,7 @@ __global__ __launch_bounds__(256) void k_seam(const SeamInst<T> *__restrict__ in
     if (mine) {
       T v[NC];
       if (is_seam<TX, TY, TZ>(qx, qy, qz)) {
-        seam_sum<T, NC, TX, TY, TZ>(a, rs, m, qx, qy, qz, v);
+        seam_sum<T, NC, TX, TY, TZ>(a, rs, partial_block<T, NC, TX, TY, TZ>(a, m), qx, qy, qz, v);
       } else {
 #pragma unroll
         for (int c = 0; c < NC; ++c) v[c] = yi[slot + c * a.n_local];
