@@ -203,21 +203,34 @@ def n_elements(mesh_nt, level):
     return mesh_nt * n ** 3
 
 
+KERNEL_SOURCES = ("kernels_tile.hip", "tmf_internal.h")
+
+
+def kernel_code_hash(sources=KERNEL_SOURCES):
+    """Hash of the element kernels' code with comments and whitespace removed: counters taken
+    on one version stay valid across edits of its comments, and only those."""
+    import re
+    h = hashlib.sha256()
+    for name in sources:
+        with open(os.path.join(ROOT, "paper_2404_08371_amd", "csrc", name)) as f:
+            txt = f.read()
+        txt = re.sub(r"/\*.*?\*/", " ", txt, flags=re.S)
+        txt = re.sub(r"//[^\n]*", " ", txt)
+        h.update(name.encode() + b"\0" + " ".join(txt.split()).encode() + b"\0")
+    return h.hexdigest()[:16]
+
+
 def traffic_for(kernel_key, tile):
     """HBM bytes per launch of one element-kernel tile shape, from the committed rocprofv3 counter runs
     (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a 1 GiB copy); None when the kernel
-    source has changed since the counters were taken."""
+    code has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         data = json.load(f)
     ent = data.get(kernel_key)
-    if not ent:
-        return None
-    src = os.path.join(ROOT, "paper_2404_08371_amd", "csrc", ent["source"])
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if h != ent.get("source_sha256_16"):
+    if not ent or kernel_code_hash(tuple(ent.get("sources", ()))) != ent.get("code_sha256_16"):
         return None
     return ent["bytes_per_launch_by_tile"].get("x".join(str(v) for v in tile))
 

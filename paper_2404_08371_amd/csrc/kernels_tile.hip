@@ -1207,14 +1207,16 @@ __device__ __forceinline__ void seam_sum(const SeamInst<T> &a, RS rs, GPtr<const
 }
 
 // Work entries: (instance, macro, first seam point, 0) reduce up to 256 PPT
-// seam points of one macro (PPT set by how the work list was chunked); (instance, first member, end member, 1) reduce whole
-// interface groups, one thread per member (at most 256 members).  The tile-row
+// seam points of one macro (PPT set by how the work list was chunked);
+// (instance, first member, end member, 1) reduce whole interface groups, one
+// thread per member (at most 256 members).  The tile-row
 // starts of the instance are staged in dynamic LDS (`rows_lds` entries; a
-// larger table is read from global memory).
+// larger table is read from global memory).  At most 96 VGPRs (5 waves per
+// SIMD): a launch of up to 1280 work entries is then resident at once.
 template <typename T, int NC, int PPT, int TX, int TY, int TZ>
-__global__ __launch_bounds__(256, 5) void k_seam(const SeamInst<T> *__restrict__ insts, const int4 *__restrict__ work,
-                                              T *__restrict__ y, const uint8_t *__restrict__ active, int flags,
-                                              int rows_lds) {
+__global__ __launch_bounds__(256, 5) void k_seam(const SeamInst<T> *__restrict__ insts,
+                                                 const int4 *__restrict__ work, T *__restrict__ y,
+                                                 const uint8_t *__restrict__ active, int flags, int rows_lds) {
   const bool local = flags & kSeamLocal;
   extern __shared__ int srs[];
   __shared__ T sv[NC][256];
