@@ -206,13 +206,14 @@ def n_elements(mesh_nt, level):
 KERNEL_SOURCES = ("kernels_tile.hip", "tmf_internal.h")
 
 
-def kernel_code_hash(sources=KERNEL_SOURCES):
+def kernel_code_hash(sources=KERNEL_SOURCES, csrc=None):
     """Hash of the element kernels' code with comments and whitespace removed: counters taken
     on one version stay valid across edits of its comments, and only those."""
     import re
+    csrc = csrc or os.path.join(ROOT, "paper_2404_08371_amd", "csrc")
     h = hashlib.sha256()
     for name in sources:
-        with open(os.path.join(ROOT, "paper_2404_08371_amd", "csrc", name)) as f:
+        with open(os.path.join(csrc, name)) as f:
             txt = f.read()
         txt = re.sub(r"/\*.*?\*/", " ", txt, flags=re.S)
         txt = re.sub(r"//[^\n]*", " ", txt)
