@@ -485,12 +485,12 @@ tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const
     std::vector<int4> ch;
     const int N = S.N;
     if (kind == P1_LAPLACE) {
-      // stencil tiles (2.5-D blocking): rows j0 .. j0+3, points i0 .. i0+61,
-      // planes k0 .. k0+3 (the planes where the tile has points).  i0 varies
-      // fastest: concurrent wavefronts cover whole rows of the same planes,
-      // so memory is read in long contiguous runs.
+      // stencil tiles (2.5-D blocking): rows j0 .. j0+kStencilRows-1, points
+      // i0 .. i0+61, planes k0 .. k0+3 (the planes where the tile has
+      // points).  i0 varies fastest: concurrent wavefronts cover whole rows of
+      // the same planes, so memory is read in long contiguous runs.
       for (int k0 = 0; k0 <= N; k0 += 4)
-        for (int j0 = 0; j0 <= N - k0; j0 += 4)
+        for (int j0 = 0; j0 <= N - k0; j0 += kStencilRows)
           for (int i0 = 0; i0 <= N - j0 - k0; i0 += 62)
             ch.push_back(make_int4(j0, i0, k0, std::min(k0 + 4, N - i0 - j0 + 1)));
     } else {

@@ -373,7 +373,7 @@ __global__ __launch_bounds__(256) void k_p1_apply(P1Args<T> a, const int4 *__res
 // k-1's rows j0 .. j0+KJ and plane k+1's rows j0-1 .. j0+KJ-1; a step to
 // plane k+1 loads KJ + 2 rows (plane k+2's KJ + 1, plane k+1's row j0+KJ)
 // for KJ output rows, issued one step ahead.
-constexpr int KJ = 4;
+constexpr int KJ = kStencilRows;
 template <typename T>
 __global__ __launch_bounds__(256) void k_p1_stencil(P1Args<T> a, const int4 *__restrict__ units, int nunits) {
   const LatticeArgs<T> &L = a.lat;

@@ -228,6 +228,9 @@ hipError_t launch_interface_sum(const GroupArgs &g, T *y, hipStream_t s);
 template <typename T>
 hipError_t launch_fill(T *p, int64_t n, T v, hipStream_t s);
 
+// rows per wavefront of the constant-coefficient P1 stencil (2.5-D blocking)
+constexpr int kStencilRows = 4;
+
 // tile shapes available to the element-centric kernels (micro-cubes per tile)
 constexpr int kNumTileCfg = 4;
 constexpr int kTileCfg[kNumTileCfg][3] = {{4, 4, 4}, {8, 4, 2}, {8, 4, 4}, {4, 4, 8}};
