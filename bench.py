@@ -55,9 +55,14 @@ FLOPS = {
     "p2_stored": 200,          # per micro-tet: symmetric 10 x 10 matrix-vector product from 55 stored entries
     "p2_quad_per_q": 60,       # per micro-tet and quadrature point: k(q) (10 FMA) and 10 weight updates
     "p2_no_weights": 266,      # per micro-tet: the quadrature-variant apply without its weights (h = sp Gp form)
-    "eps_blended_per_q": 657,  # per micro-tet and quadrature point (map Jacobian, inverse, 2 x 90-term contractions)
-    "eps_blended_adjoint_per_q": 1337,  # forward of gy (657) + mu gradient (680: map Jacobian and inverse,
-                                        # gradients of x and gy, strain contraction, 10-node scatter)
+    "eps_blended_per_q": 435,  # per micro-tet and quadrature point: map Jacobian and inverse (160), reference
+                               # gradients from their P1 coefficients (63), physical gradients (45), mu (19),
+                               # stress (30), pull-back (45), 4 x 9 output accumulators (72)
+    "eps_blended_per_elem": 240,        # per micro-tet once: 3 x gradient coefficients, 3 x P2 output map
+    "eps_blended_adjoint_per_q": 888,   # forward of gy (435) + mu gradient (453: map Jacobian and inverse,
+                                        # gradients of x and gy from P1 coefficients, strain contraction,
+                                        # 10-node scatter)
+    "eps_blended_adjoint_per_elem": 480,  # forward (240) + 6 x gradient coefficients of the mu gradient
 }
 
 
@@ -523,11 +528,13 @@ def main():
         for prec, nm, pk, bpd in ((T.F64, "fp64", PEAK_FP64, 8), (T.F32, "fp32", PEAK_FP32, 4)):
             oe = T.Operator(ms6, T.P2V_EPSILON, prec, T.BC_DIRICHLET_ZERO, rule=rule)
             form("eps_blended_%s_shell_l6" % nm, ms6, oe, "eps", 4,
-                 n_elements(24, 6) * 14 * FLOPS["eps_blended_per_q"], 7 * bpd * oe.n_local, pk, 5)
+                 n_elements(24, 6) * (14 * FLOPS["eps_blended_per_q"] + FLOPS["eps_blended_per_elem"]),
+                 7 * bpd * oe.n_local, pk, 5)
             if prec == T.F64:
                 # adjoint: gx = L(mu) gy and the mu gradient (gy, mu -> gx; x, gy -> gmu)
                 form("eps_blended_adjoint_fp64_shell_l6", ms6, oe, "eps", 4,
-                     n_elements(24, 6) * 14 * FLOPS["eps_blended_adjoint_per_q"], 14 * bpd * oe.n_local, pk, 5,
+                     n_elements(24, 6) * (14 * FLOPS["eps_blended_adjoint_per_q"]
+                                          + FLOPS["eps_blended_adjoint_per_elem"]), 14 * bpd * oe.n_local, pk, 5,
                      adjoint=True)
             del oe
         # batched mixed-precision solve: 32 reference-tet instances, levels in {3..7}

@@ -374,21 +374,8 @@ void fill_qtab(const double *qb, const double *qw, int nq, std::vector<T> &out) 
     const double *l = qb + 4 * q;
     Q[0] = T(qw[q]);
     for (int a = 0; a < 4; ++a) Q[1 + a] = T(l[a]);
-    double phi[10], dphi[10][4] = {{0}};
-    for (int a = 0; a < 4; ++a) {
-      phi[a] = l[a] * (2 * l[a] - 1);
-      dphi[a][a] = 4 * l[a] - 1;
-    }
-    for (int e = 0; e < 6; ++e) {
-      const int a = kEdge[e][0], b = kEdge[e][1];
-      phi[4 + e] = 4 * l[a] * l[b];
-      dphi[4 + e][a] = 4 * l[b];
-      dphi[4 + e][b] = 4 * l[a];
-    }
-    for (int i = 0; i < 10; ++i) {
-      Q[5 + i] = T(phi[i]);
-      for (int r = 0; r < 3; ++r) Q[15 + 3 * i + r] = T(dphi[i][r + 1] - dphi[i][0]);
-    }
+    for (int a = 0; a < 4; ++a) Q[5 + a] = T(l[a] * (2 * l[a] - 1));
+    for (int e = 0; e < 6; ++e) Q[9 + e] = T(4 * l[kEdge[e][0]] * l[kEdge[e][1]]);
   }
 }
 

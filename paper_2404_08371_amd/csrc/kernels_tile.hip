@@ -416,12 +416,28 @@ __device__ inline void eps_elem(const T u[3][10], const T mu[10], CPtr<T> grad, 
 template <typename T>
 __device__ inline void eps_blended_elem(const T u[3][10], const T mu[10], const T P0[3], CPtr<T> JT,
                                         const T s[3], CPtr<T> qtab, int nq, T y[3][10]) {
+  // The reference gradient of a P2 field is a P1 field: grad_ref u_c(q) =
+  // sum_a lambda_a(q) G[c][a], G[c][a] = the gradient coefficients of
+  // grad_coeffs (the reference gradients of lambda_1..3 are the unit
+  // vectors).  Likewise every basis gradient is linear in lambda, so the
+  // outputs need only Ta[d][a] = sum_q lambda_a(q) S_q[d] (S_q the weighted
+  // stress pulled back to the reference tet), and after the loop the P2
+  // output map of p2_elem with sigma[a][b] = Ta[d][a] . grad_ref lambda_b.
+  // Per point this takes 36 + 36 multiply-adds where the nodal forms take
+  // 90 + 90.
+  T G[3][4][3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
+  for (int c = 0; c < 3; ++c) grad_coeffs(u[c], G[c]);
+  T Ta[3][4][3];
 #pragma unroll
-    for (int i = 0; i < 10; ++i) y[c][i] = T(0);
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) Ta[d][a][r] = T(0);
   for (int q = 0; q < nq; ++q) {
-    CPtr<T> Q = qtab + q * kQStride;  // w, bary[4], phi[10], refgrad[10][3]
+    CPtr<T> Q = qtab + q * kQStride;  // w, bary[4], phi[10]
+    const T lam[4] = {Q[1], Q[2], Q[3], Q[4]};
     const T xh[3] = {Q[2], Q[3], Q[4]};
     T xi[3];
 #pragma unroll
@@ -457,17 +473,12 @@ __device__ inline void eps_blended_elem(const T u[3][10], const T mu[10], const 
     for (int r = 0; r < 3; ++r)
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) Ji[r][cc] *= idet;
-    CPtr<T> RG = Q + 15;
     T gr[3][3];  // reference gradient of each component
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        T acc = T(0);
-#pragma unroll
-        for (int i = 0; i < 10; ++i) acc += u[c][i] * RG[3 * i + r];
-        gr[c][r] = acc;
-      }
+      for (int r = 0; r < 3; ++r)
+        gr[c][r] = lam[0] * G[c][0][r] + lam[1] * G[c][1][r] + lam[2] * G[c][2][r] + lam[3] * G[c][3][r];
     T gu[3][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -482,15 +493,32 @@ __device__ inline void eps_blended_elem(const T u[3][10], const T mu[10], const 
     for (int d = 0; d < 3; ++d)
 #pragma unroll
       for (int e = 0; e < 3; ++e) sg[d][e] = f * T(0.5) * (gu[d][e] + gu[e][d]);
-    T S[3][3];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
-      for (int r = 0; r < 3; ++r) S[d][r] = sg[d][0] * Ji[r][0] + sg[d][1] * Ji[r][1] + sg[d][2] * Ji[r][2];
+      for (int r = 0; r < 3; ++r) {
+        const T S = sg[d][0] * Ji[r][0] + sg[d][1] * Ji[r][1] + sg[d][2] * Ji[r][2];
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+        for (int a = 0; a < 4; ++a) Ta[d][a][r] += lam[a] * S;
+      }
+  }
 #pragma unroll
-      for (int i = 0; i < 10; ++i) y[d][i] += S[d][0] * RG[3 * i + 0] + S[d][1] * RG[3 * i + 1] + S[d][2] * RG[3 * i + 2];
+  for (int d = 0; d < 3; ++d) {
+    T sig[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      sig[a][1] = Ta[d][a][0];
+      sig[a][2] = Ta[d][a][1];
+      sig[a][3] = Ta[d][a][2];
+      sig[a][0] = -(sig[a][1] + sig[a][2] + sig[a][3]);
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) y[d][b] = T(4) * sig[b][b] - (sig[0][b] + sig[1][b] + sig[2][b] + sig[3][b]);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      const int b = kEdge[e][0], c = kEdge[e][1];
+      y[d][4 + e] = T(4) * (sig[c][b] + sig[b][c]);
+    }
   }
 }
 
@@ -590,10 +618,17 @@ __device__ inline void eps_gradmu(const T u[3][10], const T gy[3][10], CPtr<T> g
 template <typename T>
 __device__ inline void eps_blended_gradmu(const T u[3][10], const T gy[3][10], const T P0[3], CPtr<T> JT,
                                           const T s[3], CPtr<T> qtab, int nq, T gmu[10]) {
+  T Gu[3][4][3], Gg[3][4][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    grad_coeffs(u[c], Gu[c]);
+    grad_coeffs(gy[c], Gg[c]);
+  }
 #pragma unroll
   for (int i = 0; i < 10; ++i) gmu[i] = T(0);
   for (int q = 0; q < nq; ++q) {
-    CPtr<T> Q = qtab + q * kQStride;  // w, bary[4], phi[10], refgrad[10][3]
+    CPtr<T> Q = qtab + q * kQStride;  // w, bary[4], phi[10]
+    const T lam[4] = {Q[1], Q[2], Q[3], Q[4]};
     const T xh[3] = {Q[2], Q[3], Q[4]};
     T xi[3];
 #pragma unroll
@@ -629,22 +664,16 @@ __device__ inline void eps_blended_gradmu(const T u[3][10], const T gy[3][10], c
     for (int r = 0; r < 3; ++r)
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) Ji[r][cc] *= idet;
-    CPtr<T> RG = Q + 15;
-    // physical gradients of u and gy
+    // physical gradients of u and gy (reference gradients as P1 fields, as in
+    // eps_blended_elem)
     T gu[3][3], gg[3][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       T ru[3], rg[3];
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
-        T au = T(0), ag = T(0);
-#pragma unroll
-        for (int i = 0; i < 10; ++i) {
-          au += u[c][i] * RG[3 * i + r];
-          ag += gy[c][i] * RG[3 * i + r];
-        }
-        ru[r] = au;
-        rg[r] = ag;
+        ru[r] = lam[0] * Gu[c][0][r] + lam[1] * Gu[c][1][r] + lam[2] * Gu[c][2][r] + lam[3] * Gu[c][3][r];
+        rg[r] = lam[0] * Gg[c][0][r] + lam[1] * Gg[c][1][r] + lam[2] * Gg[c][2][r] + lam[3] * Gg[c][3][r];
       }
 #pragma unroll
       for (int d = 0; d < 3; ++d) {

@@ -155,7 +155,7 @@ struct TileArgs {
   const int4 *tiles;
   int ntiles;
   const uint8_t *active;  // per instance, NULL = all active; tiles of inactive instances are skipped
-  const T *qtab;          // blended map: per quadrature point [w, bary(4), phi(10), refgrad(30)]
+  const T *qtab;          // quadrature rule: per point [w, bary(4), phi(10)]
   int nq;
   const T *k;
   const T *x;
@@ -172,7 +172,7 @@ struct GroupArgs {
   int ncomp;
 };
 
-constexpr int kQStride = 45;  // floats per quadrature point in qtab
+constexpr int kQStride = 15;  // values per quadrature point in qtab
 
 // Seam and interface reduction, one launch for a whole batch.  y at every
 // seam point (a lattice point on a face shared by tile boxes) = the
