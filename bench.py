@@ -55,14 +55,14 @@ FLOPS = {
     "p2_stored": 200,          # per micro-tet: symmetric 10 x 10 matrix-vector product from 55 stored entries
     "p2_quad_per_q": 60,       # per micro-tet and quadrature point: k(q) (10 FMA) and 10 weight updates
     "p2_no_weights": 266,      # per micro-tet: the quadrature-variant apply without its weights (h = sp Gp form)
-    "eps_blended_per_q": 435,  # per micro-tet and quadrature point: map Jacobian and inverse (160), reference
-                               # gradients from their P1 coefficients (63), physical gradients (45), mu (19),
-                               # stress (30), pull-back (45), 4 x 9 output accumulators (72)
-    "eps_blended_per_elem": 240,        # per micro-tet once: 3 x gradient coefficients, 3 x P2 output map
-    "eps_blended_adjoint_per_q": 888,   # forward of gy (435) + mu gradient (453: map Jacobian and inverse,
+    "eps_blended_per_q": 321,  # per micro-tet and quadrature point: map point and its closed-form inverse (44),
+                               # gradients in xi from P1 coefficients and pulled through the inverse (108), mu (19),
+                               # stress (33), pulled back and added to 4 x 9 accumulators (117)
+    "eps_blended_per_elem": 600,        # per micro-tet once: 3 x gradient coefficients in xi, 3 x P2 output map
+    "eps_blended_adjoint_per_q": 774,   # forward of gy (321) + mu gradient (453: map Jacobian and inverse,
                                         # gradients of x and gy from P1 coefficients, strain contraction,
                                         # 10-node scatter)
-    "eps_blended_adjoint_per_elem": 480,  # forward (240) + 6 x gradient coefficients of the mu gradient
+    "eps_blended_adjoint_per_elem": 840,  # forward (600) + 6 x gradient coefficients of the mu gradient
 }
 
 

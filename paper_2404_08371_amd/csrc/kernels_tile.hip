@@ -413,103 +413,106 @@ __device__ inline void eps_elem(const T u[3][10], const T mu[10], CPtr<T> grad, 
 //   xi_q = P0 + JT xhat_q, J = DPhi(xi_q) JT,
 //   grad u_c = (ref-grad u_c) J^-1,  sigma = 2 mu_q w_q |det J| sym(grad u),
 //   y_(i,d) += sum_r (sigma J^-T)_(d r) ref-grad_r phi_i(xhat_q).
+// DPhi = a0 I + xi v^T with a0 = rho/|xi|, rho = s.xi > 0 and
+// v = s/|xi| - rho xi/|xi|^3.  Since v.xi = 0, DPhi^-1 = (I - xi v^T/a0)/a0
+// and det DPhi = a0^3; J^-1 = JT^-1 DPhi^-1, whose first factor is the
+// micro-tet's (constant) barycentric gradients.
 template <typename T>
-__device__ inline void eps_blended_elem(const T u[3][10], const T mu[10], const T P0[3], CPtr<T> JT,
-                                        const T s[3], CPtr<T> qtab, int nq, T y[3][10]) {
-  // The reference gradient of a P2 field is a P1 field: grad_ref u_c(q) =
-  // sum_a lambda_a(q) G[c][a], G[c][a] = the gradient coefficients of
-  // grad_coeffs (the reference gradients of lambda_1..3 are the unit
-  // vectors).  Likewise every basis gradient is linear in lambda, so the
-  // outputs need only Ta[d][a] = sum_q lambda_a(q) S_q[d] (S_q the weighted
-  // stress pulled back to the reference tet), and after the loop the P2
-  // output map of p2_elem with sigma[a][b] = Ta[d][a] . grad_ref lambda_b.
-  // Per point this takes 36 + 36 multiply-adds where the nodal forms take
-  // 90 + 90.
-  T G[3][4][3];
+__device__ __forceinline__ T shell_map(const T P0[3], CPtr<T> JT, const T s[3], const T xh[3], T xi[3], T v[3]) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) grad_coeffs(u[c], G[c]);
-  T Ta[3][4][3];
+  for (int d = 0; d < 3; ++d) xi[d] = P0[d] + JT[3 * d + 0] * xh[0] + JT[3 * d + 1] * xh[1] + JT[3 * d + 2] * xh[2];
+  const T rho = s[0] * xi[0] + s[1] * xi[1] + s[2] * xi[2];
+  const T n2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+  const T inv = T(1) / sqrt(n2);
+  const T c3i = rho * inv * inv * inv;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) v[d] = s[d] * inv - c3i * xi[d];
+  return rho * inv;
+}
+
+// g = h (I - p q^T / a0) / a0 for a row vector h: with (p, q) = (xi, v) this
+// is h DPhi^-1, with (p, q) = (v, xi) it is h DPhi^-T
+template <typename T>
+__device__ __forceinline__ void shell_pull(const T h[3], const T p[3], const T q[3], T ia0, T g[3]) {
+  const T t = (h[0] * p[0] + h[1] * p[1] + h[2] * p[2]) * ia0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) g[d] = ia0 * (h[d] - t * q[d]);
+}
+
+// Gradient coefficients of a P2 field in xi coordinates (the affine part of
+// the map): grad_xi u(q) = sum_a lambda_a(q) H[a], H[a] = sum_b s[a][b] grad lambda_b
+template <typename T>
+__device__ __forceinline__ void xi_grad_coeffs(const T u[10], CPtr<T> gl, T H[4][3]) {
+  T sp[4][3];
+  grad_coeffs(u, sp);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) H[a][d] = sp[a][0] * gl[3 + d] + sp[a][1] * gl[6 + d] + sp[a][2] * gl[9 + d];
+}
+
+template <typename T>
+__device__ inline void eps_blended_elem(const T u[3][10], const T mu[10], const T P0[3], CPtr<T> JT, CPtr<T> gl,
+                                        T vol, const T s[3], CPtr<T> qtab, int nq, T y[3][10]) {
+  // Every gradient is linear in lambda on the affine part of the map: the
+  // gradient of u_c in xi coordinates is sum_a lambda_a(q) H[c][a]; the
+  // outputs need only Tx[d][a] = sum_q lambda_a(q) (sigma_q DPhi^-T)_d,
+  // mapped after the loop by the P2 output rule of p2_elem with
+  // sigma[a][b] = Tx[d][a] . grad lambda_b.
+  T H[3][4][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) xi_grad_coeffs(u[c], gl, H[c]);
+  T Tx[3][4][3];
 #pragma unroll
   for (int d = 0; d < 3; ++d)
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int r = 0; r < 3; ++r) Ta[d][a][r] = T(0);
+      for (int r = 0; r < 3; ++r) Tx[d][a][r] = T(0);
+  const T vol6 = T(6) * vol;
   for (int q = 0; q < nq; ++q) {
     CPtr<T> Q = qtab + q * kQStride;  // w, bary[4], phi[10]
     const T lam[4] = {Q[1], Q[2], Q[3], Q[4]};
     const T xh[3] = {Q[2], Q[3], Q[4]};
-    T xi[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) xi[d] = P0[d] + JT[3 * d + 0] * xh[0] + JT[3 * d + 1] * xh[1] + JT[3 * d + 2] * xh[2];
-    const T rho = s[0] * xi[0] + s[1] * xi[1] + s[2] * xi[2];
-    const T n2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
-    const T inv = T(1) / sqrt(n2);
-    const T a0 = rho * inv;
-    const T c3i = rho * inv * inv * inv;
-    T D[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) D[r][cc] = xi[r] * (s[cc] * inv - c3i * xi[cc]) + (r == cc ? a0 : T(0));
-    T J[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) J[r][cc] = D[r][0] * JT[0 + cc] + D[r][1] * JT[3 + cc] + D[r][2] * JT[6 + cc];
-    T Ji[3][3];
-    Ji[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-    Ji[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-    Ji[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-    Ji[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-    Ji[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-    Ji[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-    Ji[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-    Ji[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-    Ji[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-    const T det = J[0][0] * Ji[0][0] + J[0][1] * Ji[1][0] + J[0][2] * Ji[2][0];
-    const T idet = T(1) / det;
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) Ji[r][cc] *= idet;
-    T gr[3][3];  // reference gradient of each component
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-        gr[c][r] = lam[0] * G[c][0][r] + lam[1] * G[c][1][r] + lam[2] * G[c][2][r] + lam[3] * G[c][3][r];
+    T xi[3], v[3];
+    const T a0 = shell_map(P0, JT, s, xh, xi, v);
+    const T ia0 = T(1) / a0;
     T gu[3][3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 3; ++c) {
+      T h[3];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) gu[c][d] = gr[c][0] * Ji[0][d] + gr[c][1] * Ji[1][d] + gr[c][2] * Ji[2][d];
+      for (int r = 0; r < 3; ++r)
+        h[r] = lam[0] * H[c][0][r] + lam[1] * H[c][1][r] + lam[2] * H[c][2][r] + lam[3] * H[c][3][r];
+      shell_pull(h, xi, v, ia0, gu[c]);
+    }
     T muq = T(0);
 #pragma unroll
     for (int i = 0; i < 10; ++i) muq += mu[i] * Q[5 + i];
-    const T f = T(2) * muq * Q[0] * fabs(det);
+    const T f = T(2) * muq * Q[0] * (a0 * a0 * a0 * vol6);
     T sg[3][3];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
       for (int e = 0; e < 3; ++e) sg[d][e] = f * T(0.5) * (gu[d][e] + gu[e][d]);
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+    for (int d = 0; d < 3; ++d) {
+      T Sx[3];
+      shell_pull(sg[d], v, xi, ia0, Sx);
 #pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const T S = sg[d][0] * Ji[r][0] + sg[d][1] * Ji[r][1] + sg[d][2] * Ji[r][2];
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int a = 0; a < 4; ++a) Ta[d][a][r] += lam[a] * S;
-      }
+        for (int r = 0; r < 3; ++r) Tx[d][a][r] += lam[a] * Sx[r];
+    }
   }
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     T sig[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      sig[a][1] = Ta[d][a][0];
-      sig[a][2] = Ta[d][a][1];
-      sig[a][3] = Ta[d][a][2];
+#pragma unroll
+      for (int b = 1; b < 4; ++b)
+        sig[a][b] = Tx[d][a][0] * gl[3 * b + 0] + Tx[d][a][1] * gl[3 * b + 1] + Tx[d][a][2] * gl[3 * b + 2];
       sig[a][0] = -(sig[a][1] + sig[a][2] + sig[a][3]);
     }
 #pragma unroll
@@ -838,7 +841,7 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
       for (int d = 0; d < 3; ++d)
         P0[d] = mg.v0[d] + (mg.JM[3 * d + 0] * bc[0] + mg.JM[3 * d + 1] * bc[1] + mg.JM[3 * d + 2] * bc[2]) * inv_n;
       const T sv[3] = {mg.s[0], mg.s[1], mg.s[2]};
-      eps_blended_elem(u, mu, P0, cptr(g->JT), sv, cptr(a.qtab), a.nq, y);
+      eps_blended_elem(u, mu, P0, cptr(g->JT), cptr(g->grad), *cptr(&g->vol), sv, cptr(a.qtab), a.nq, y);
     }
 #pragma unroll
     for (int v = 0; v < 10; ++v)
