@@ -59,10 +59,10 @@ FLOPS = {
                                # gradients in xi from P1 coefficients and pulled through the inverse (108), mu (19),
                                # stress (33), pulled back and added to 4 x 9 accumulators (117)
     "eps_blended_per_elem": 600,        # per micro-tet once: 3 x gradient coefficients in xi, 3 x P2 output map
-    "eps_blended_adjoint_per_q": 774,   # forward of gy (321) + mu gradient (453: map Jacobian and inverse,
-                                        # gradients of x and gy from P1 coefficients, strain contraction,
-                                        # 10-node scatter)
-    "eps_blended_adjoint_per_elem": 840,  # forward (600) + 6 x gradient coefficients of the mu gradient
+    "eps_blended_adjoint_per_q": 644,   # forward of gy (321) + mu gradient (323: map point and inverse, gradient
+                                        # of x pulled through it, its symmetric part pushed through the transpose
+                                        # and contracted with the gradient of gy in xi, 10-node scatter)
+    "eps_blended_adjoint_per_elem": 1200,  # forward (600) + 6 x gradient coefficients in xi of the mu gradient
 }
 
 

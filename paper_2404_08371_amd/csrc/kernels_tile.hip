@@ -620,77 +620,47 @@ __device__ inline void eps_gradmu(const T u[3][10], const T gy[3][10], CPtr<T> g
 // gmu_b = sum_q phi_b(q) 2 w_q |det J| eps(u_q) : eps(gy_q).
 template <typename T>
 __device__ inline void eps_blended_gradmu(const T u[3][10], const T gy[3][10], const T P0[3], CPtr<T> JT,
-                                          const T s[3], CPtr<T> qtab, int nq, T gmu[10]) {
-  T Gu[3][4][3], Gg[3][4][3];
+                                          CPtr<T> gl, T vol, const T s[3], CPtr<T> qtab, int nq, T gmu[10]) {
+  // eps(u) : eps(gy) = sym(grad u) : grad gy = sum_c (sym(grad u)_c DPhi^-T) . hg_c
+  // with hg_c the gradient of gy_c in xi coordinates: only the gradient of u
+  // goes through DPhi^-1 (map and coefficients as in eps_blended_elem)
+  T Hu[3][4][3], Hg[3][4][3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    grad_coeffs(u[c], Gu[c]);
-    grad_coeffs(gy[c], Gg[c]);
+    xi_grad_coeffs(u[c], gl, Hu[c]);
+    xi_grad_coeffs(gy[c], gl, Hg[c]);
   }
 #pragma unroll
   for (int i = 0; i < 10; ++i) gmu[i] = T(0);
+  const T vol6 = T(6) * vol;
   for (int q = 0; q < nq; ++q) {
     CPtr<T> Q = qtab + q * kQStride;  // w, bary[4], phi[10]
     const T lam[4] = {Q[1], Q[2], Q[3], Q[4]};
     const T xh[3] = {Q[2], Q[3], Q[4]};
-    T xi[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) xi[d] = P0[d] + JT[3 * d + 0] * xh[0] + JT[3 * d + 1] * xh[1] + JT[3 * d + 2] * xh[2];
-    const T rho = s[0] * xi[0] + s[1] * xi[1] + s[2] * xi[2];
-    const T n2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
-    const T inv = T(1) / sqrt(n2);
-    const T a0 = rho * inv;
-    const T c3i = rho * inv * inv * inv;
-    T D[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) D[r][cc] = xi[r] * (s[cc] * inv - c3i * xi[cc]) + (r == cc ? a0 : T(0));
-    T J[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) J[r][cc] = D[r][0] * JT[0 + cc] + D[r][1] * JT[3 + cc] + D[r][2] * JT[6 + cc];
-    T Ji[3][3];
-    Ji[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-    Ji[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-    Ji[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-    Ji[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-    Ji[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-    Ji[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-    Ji[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-    Ji[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-    Ji[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-    const T det = J[0][0] * Ji[0][0] + J[0][1] * Ji[1][0] + J[0][2] * Ji[2][0];
-    const T idet = T(1) / det;
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) Ji[r][cc] *= idet;
-    // physical gradients of u and gy (reference gradients as P1 fields, as in
-    // eps_blended_elem)
-    T gu[3][3], gg[3][3];
+    T xi[3], v[3];
+    const T a0 = shell_map(P0, JT, s, xh, xi, v);
+    const T ia0 = T(1) / a0;
+    T gu[3][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      T ru[3], rg[3];
+      T h[3];
 #pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        ru[r] = lam[0] * Gu[c][0][r] + lam[1] * Gu[c][1][r] + lam[2] * Gu[c][2][r] + lam[3] * Gu[c][3][r];
-        rg[r] = lam[0] * Gg[c][0][r] + lam[1] * Gg[c][1][r] + lam[2] * Gg[c][2][r] + lam[3] * Gg[c][3][r];
-      }
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        gu[c][d] = ru[0] * Ji[0][d] + ru[1] * Ji[1][d] + ru[2] * Ji[2][d];
-        gg[c][d] = rg[0] * Ji[0][d] + rg[1] * Ji[1][d] + rg[2] * Ji[2][d];
-      }
+      for (int r = 0; r < 3; ++r)
+        h[r] = lam[0] * Hu[c][0][r] + lam[1] * Hu[c][1][r] + lam[2] * Hu[c][2][r] + lam[3] * Hu[c][3][r];
+      shell_pull(h, xi, v, ia0, gu[c]);
     }
-    // eps(u) : eps(gy) = sum_{d,e} sym(gu)_de sym(gg)_de
     T ee = T(0);
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+    for (int c = 0; c < 3; ++c) {
+      T sc[3], px[3];
 #pragma unroll
-      for (int e = 0; e < 3; ++e) ee += T(0.25) * (gu[d][e] + gu[e][d]) * (gg[d][e] + gg[e][d]);
-    const T f = T(2) * Q[0] * fabs(det) * ee;
+      for (int d = 0; d < 3; ++d) sc[d] = T(0.5) * (gu[c][d] + gu[d][c]);
+      shell_pull(sc, v, xi, ia0, px);
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+        ee += px[r] * (lam[0] * Hg[c][0][r] + lam[1] * Hg[c][1][r] + lam[2] * Hg[c][2][r] + lam[3] * Hg[c][3][r]);
+    }
+    const T f = T(2) * Q[0] * (a0 * a0 * a0 * vol6) * ee;
 #pragma unroll
     for (int i = 0; i < 10; ++i) gmu[i] += f * Q[5 + i];
   }
@@ -926,7 +896,7 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
       for (int d = 0; d < 3; ++d)
         P0[d] = mg.v0[d] + (mg.JM[3 * d + 0] * bc[0] + mg.JM[3 * d + 1] * bc[1] + mg.JM[3 * d + 2] * bc[2]) * inv_n;
       const T sv[3] = {mg.s[0], mg.s[1], mg.s[2]};
-      eps_blended_gradmu(u, gv, P0, cptr(g->JT), sv, cptr(a.qtab), a.nq, gm);
+      eps_blended_gradmu(u, gv, P0, cptr(g->JT), cptr(g->grad), *cptr(&g->vol), sv, cptr(a.qtab), a.nq, gm);
     }
 #pragma unroll
     for (int v = 0; v < 10; ++v) atomicAdd(&sy[0][li[v]], double(gm[v]));
