@@ -45,3 +45,4 @@ def test_multi_gpu_request_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
