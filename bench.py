@@ -48,8 +48,9 @@ FLOPS = {
     "p1_laplace": 30,          # per DoF: 15-point stencil
     "p1_divkgrad": 312,        # per DoF: 24 incident micro-tets x (4x4 row, mean k, accumulate)
     "p1_adjoint": 1200,        # per DoF: forward row (312) + 24 x bilinear form (37)
-    "p2_adjoint": 864,         # per micro-tet: forward apply of gy (276) + coefficient gradient (588:
-                               # gradient coefficients 40, h 72, Gam 44, M 112, 10 x 16-term contractions 320)
+    "p2_adjoint": 625,         # per micro-tet: forward apply of gy (276) + coefficient gradient (349:
+                               # gradient coefficients 40, h 72, Gam 44, M 112, closed-form derivative of the
+                               # collected weights 81)
     "eps_affine": 970,         # per micro-tet
     "n1": 440,                 # per micro-tet: 6 curls, curl u, curl part, U_p, B (beta weights), V, mass part
     "p2_stored": 200,          # per micro-tet: symmetric 10 x 10 matrix-vector product from 55 stored entries

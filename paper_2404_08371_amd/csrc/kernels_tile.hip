@@ -323,19 +323,26 @@ __device__ inline void p2_gradk(const T u[10], const T g[10], CPtr<T> Gp, T gk[1
 #pragma unroll
     for (int e = 0; e < 4; ++e)
       M[c][e] = h[c][0] * gam[e][0] + h[c][1] * gam[e][1] + h[c][2] * gam[e][2] + h[c][3] * gam[e][3];
+  // With the collected weights of weights_p2_840, 840 sum W M =
+  // sum_edges 4 k_ce P_ce + sum_c b_c Z_c + sum_c 8 k_c M_cc (P_ce = M_ce + M_ec,
+  // Z_c = sum_{e != c} P_ce + 4 M_cc), whose derivatives are
+  //   840 gk_c  = Z_c + 8 M_cc - 3/2 sum Z,
+  //   840 gk_ce = 4 P_ce + 4 (Z_c + Z_e) + 2 sum Z.
+  T P[6];
 #pragma unroll
-  for (int b = 0; b < 10; ++b) {
-    T kb[10], Wb[4][4];
+  for (int e = 0; e < 6; ++e) P[e] = M[kEdge[e][0]][kEdge[e][1]] + M[kEdge[e][1]][kEdge[e][0]];
+  T Z[4];
+  Z[0] = (P[0] + P[1]) + (P[2] + T(4) * M[0][0]);
+  Z[1] = (P[0] + P[3]) + (P[4] + T(4) * M[1][1]);
+  Z[2] = (P[1] + P[3]) + (P[5] + T(4) * M[2][2]);
+  Z[3] = (P[2] + P[4]) + (P[5] + T(4) * M[3][3]);
+  const T zs = (Z[0] + Z[1]) + (Z[2] + Z[3]);
+  const T s = T(1) / T(840);
 #pragma unroll
-    for (int w = 0; w < 10; ++w) kb[w] = w == b ? T(1) : T(0);
-    weights_p2(kb, Wb);
-    T acc = T(0);
+  for (int c = 0; c < 4; ++c) gk[c] = (Z[c] + T(8) * M[c][c] - T(1.5) * zs) * s;
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) acc += Wb[c][e] * M[c][e];
-    gk[b] = acc;
-  }
+  for (int e = 0; e < 6; ++e)
+    gk[4 + e] = (T(4) * (P[e] + Z[kEdge[e][0]] + Z[kEdge[e][1]]) + T(2) * zs) * s;
 }
 
 // Fused local apply of int 2 mu eps(u):eps(v) on one affine tet.

@@ -139,3 +139,29 @@ def test_shell_map_derivative_closed_form_inverse():
         Dinv = (np.eye(3) - np.outer(xi, v) / a0) / a0
         assert np.allclose(Dinv, np.linalg.inv(D), rtol=0, atol=1e-13 * np.abs(Dinv).max())
         assert np.isclose(np.linalg.det(D), a0 ** 3, rtol=1e-13)
+
+
+def _gradk_collected(M):
+    """d(gy . y)/dk for gy . y = sum_ce W(k)_ce M_ce, from the collected weights:
+    840 gk_c = Z_c + 8 M_cc - 3/2 sum Z, 840 gk_ce = 4 P_ce + 4 (Z_c + Z_e) + 2 sum Z,
+    P_ce = M_ce + M_ec, Z_c = sum_{e != c} P_ce + 4 M_cc."""
+    P = M + M.T
+    Z = np.array([sum(P[c, e] for e in range(4) if e != c) + 4 * M[c, c] for c in range(4)])
+    g = np.zeros(10)
+    for c in range(4):
+        g[c] = Z[c] + 8 * M[c, c] - 1.5 * Z.sum()
+    for j, (c, e) in enumerate(EDGES):
+        g[4 + j] = 4 * P[c, e] + 4 * (Z[c] + Z[e]) + 2 * Z.sum()
+    return g / 840
+
+
+def test_coefficient_gradient_of_collected_weights():
+    rng = np.random.default_rng(4)
+    for _ in range(3):
+        M = rng.standard_normal((4, 4))
+        want = np.zeros(10)
+        for b in range(10):
+            kb = [Fraction(int(i == b)) for i in range(10)]
+            Wb = np.array([[float(x) for x in row] for row in _weights_exact(kb)])
+            want[b] = (Wb * M).sum()
+        assert np.allclose(_gradk_collected(M), want, rtol=0, atol=1e-14 * np.abs(want).max())
