@@ -16,6 +16,9 @@ parity tests compare the kernels themselves with the oracle).
 * The radially blended shell map: DPhi = a0 I + xi v^T with v . xi = 0, so
   DPhi^-1 = (I - xi v^T / a0) / a0 and det DPhi = a0^3, against the oracle's
   map derivative inverted by LAPACK.
+* The coefficient gradient of the P2 div(k grad) form, gk_b = W(e_b) : M, in
+  the closed form of the derivative of the collected weights, against the
+  exact weights of each unit coefficient vector.
 """
 from fractions import Fraction
 from math import factorial
