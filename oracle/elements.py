@@ -276,20 +276,42 @@ def shell_jacobian(xi, s):
     return (rho / nrm) * eye + xi[..., :, None] * (s[None, :] / nrm - rho * xi[..., None, :] / nrm ** 3)
 
 
-def eps_blended(Pxi, mu, s, qbary, qw, dmap=None):
-    """Vector P2 epsilon operator on a curved element of the radially blended shell.
+def blended_jacobians(Pxi, s, qbary, dmap=None):
+    """Jacobians of the composed element map at the points of a rule.
 
-    Pxi (...,4,3): element vertices in the flat (parametric) mesh; the physical
-    element is Phi(F_T(ref)).  At each quadrature point x_q of the reference
-    tet: xi_q = F_T(x_q), J = DPhi(xi_q) J_T, weight w_q |det J|, physical
-    gradients grad(phi) = J^-T ref-grad(phi), mu_q = sum_m mu_m phi_m(x_q).
-    `dmap(xi)` overrides the map derivative (default: the radial shell map).
+    Section "Tabulation of Factors of the Weak Form" (remark on curvilinear
+    elements): a curved element is the image Phi(F_T(x)) of the reference
+    tet, F_T the affine map of the flat micro-tet with vertices Pxi (...,4,3)
+    and Phi the blending map.  By the chain rule its Jacobian at the
+    reference point x_q is J_q = DPhi(xi_q) J_T with xi_q = F_T(x_q) (the
+    point's position in the flat mesh) and J_T = [P1-P0, P2-P0, P3-P0].
+    Returns J (...,nq,3,3).  `dmap(xi)` overrides DPhi (default: the radial
+    shell map with octant signs s).
     """
     if dmap is None:
         dmap = lambda xi: shell_jacobian(xi, s)
     Pxi = np.asarray(Pxi, dtype=np.float64)
     JT = np.stack([Pxi[..., 1, :] - Pxi[..., 0, :], Pxi[..., 2, :] - Pxi[..., 0, :],
                    Pxi[..., 3, :] - Pxi[..., 0, :]], -1)
+    out = []
+    for q in range(len(qbary)):
+        xi = np.einsum("a,...ad->...d", qbary[q], Pxi)
+        out.append(dmap(xi) @ JT)
+    return np.stack(out, -3)
+
+
+def eps_blended(Pxi, mu, s, qbary, qw, dmap=None):
+    """Vector P2 epsilon operator on a curved element of the radially blended shell.
+
+    Pxi (...,4,3): element vertices in the flat (parametric) mesh; the physical
+    element is Phi(F_T(ref)).  At each quadrature point x_q of the reference
+    tet the Jacobian is J = DPhi(F_T(x_q)) J_T (blended_jacobians), the weight
+    w_q |det J|, physical gradients grad(phi) = J^-T ref-grad(phi), and
+    mu_q = sum_m mu_m phi_m(x_q).
+    `dmap(xi)` overrides the map derivative (default: the radial shell map).
+    """
+    Pxi = np.asarray(Pxi, dtype=np.float64)
+    Jall = blended_jacobians(Pxi, s, qbary, dmap)
     vals, dv = p2_eval(qbary)
     # reference gradients: d/dx_r = d/dlambda_r - d/dlambda_0 (r = 1..3)
     dref = dv[:, :, 1:] - dv[:, :, :1]  # (nq,10,3)
@@ -297,8 +319,7 @@ def eps_blended(Pxi, mu, s, qbary, qw, dmap=None):
     A = np.zeros(sh + (30, 30))
     eye = np.eye(3)
     for q in range(len(qw)):
-        xi = np.einsum("a,...ad->...d", qbary[q], Pxi)
-        J = dmap(xi) @ JT
+        J = Jall[..., q, :, :]
         det = np.abs(np.linalg.det(J))
         Jinv = np.linalg.inv(J)
         grad = np.einsum("ir,...rd->...id", dref[q], Jinv)  # grad phi_i = J^-T ref-grad

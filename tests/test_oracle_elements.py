@@ -201,3 +201,86 @@ def test_blended_element_kills_constants_and_is_symmetric():
         u = np.zeros((3, 10))
         u[c] = 1
         assert np.abs(B @ u.ravel()).max() < 1e-12 * np.abs(B).max()
+
+
+def _shell_map(z):
+    """Radial map of the shell written out: z |z|_1 / |z|_2."""
+    return z * np.abs(z).sum() / np.linalg.norm(z)
+
+
+def _blended_by_finite_differences(P, mu, qb, qw, h=1e-5):
+    """The curved element rebuilt without the oracle's Jacobian code: J at each
+    quadrature point by central differences of the composed map
+    x -> Phi(P0 + J_T x), reference basis from sympy, strains written out."""
+    JT = (P[1:] - P[0]).T
+    G = lambda xh: _shell_map(P[0] + JT @ xh)
+    pts = qb[:, 1:]
+    vals, grads = _ref_basis(pts)
+    A = np.zeros((3, 10, 3, 10))
+    for q in range(len(qw)):
+        J = np.stack([(G(pts[q] + h * e) - G(pts[q] - h * e)) / (2 * h) for e in np.eye(3)], 1)
+        det = abs(np.linalg.det(J))
+        gphys = grads[q] @ np.linalg.inv(J)     # row i: J^-T applied to the reference gradient
+        muq = vals[q] @ mu
+        for c in range(3):
+            for i in range(10):
+                Gu = np.zeros((3, 3))
+                Gu[c] = gphys[i]
+                Eu = 0.5 * (Gu + Gu.T)
+                for d in range(3):
+                    for j in range(10):
+                        Gv = np.zeros((3, 3))
+                        Gv[d] = gphys[j]
+                        Ev = 0.5 * (Gv + Gv.T)
+                        A[d, j, c, i] += qw[q] * det * muq * 2 * np.sum(Eu * Ev)
+    return A.reshape(30, 30)
+
+
+@pytest.mark.parametrize("macro,level,tidx,which", [(0, 0, 0, 0), (7, 0, 0, 0), (13, 1, 2, 0), (22, 2, 5, 0),
+                                                    (4, 2, 3, 5), (17, 2, 0, 9)])
+def test_blended_element_matches_composed_map_finite_differences(macro, level, tidx, which):
+    """Section "Tabulation of Factors of the Weak Form" (curvilinear remark): the
+    curved element's Jacobian at a quadrature point is that of the composed map
+    Phi(F_T(x)) there.  Rebuilt from finite differences of the composed map
+    (error ~1e-10), the element matrix agrees with the oracle's to 1e-7.  A
+    Jacobian composed in the wrong order, or DPhi taken anywhere but at the
+    quadrature point, is off by O(1) on a macro and O(h) on a micro-tet."""
+    from oracle import lattice as lat
+    from workloads import meshes
+    v, t = meshes.octahedral_shell()
+    n = 2 ** level
+    pts = lat.micro_tets(n, lat.TYPE_NAMES[tidx])[which]
+    P = v[t[macro][0]] + (pts / n) @ (v[t[macro][1:]] - v[t[macro][0]])
+    s = np.sign(v[t[macro]].mean(0))
+    mu = 1 + np.random.default_rng(macro).uniform(0, 1, 10)
+    qb, qw = Q.rule_degree5()
+    B = el.eps_blended(P, mu, s, qb, qw)
+    ref = _blended_by_finite_differences(P, mu, qb, qw)
+    assert np.abs(B - ref).max() <= 1e-7 * np.abs(ref).max()
+
+
+def test_blended_shell_volume_converges():
+    """Sum over the micro-tets of the shell and the points of the rule of
+    w_q |det J_q| (the Jacobians the blended element uses) approaches the
+    volume 4/3 pi (1 - 0.55^3) of the shell the map covers exactly.  The
+    integrand |det DPhi| |det J_T| is smooth, so a degree-5 rule converges
+    at order about 6 in h; DPhi frozen at one point per element would give
+    order 2."""
+    import oracle as O
+    from workloads import meshes
+    v, t = meshes.octahedral_shell()
+    qb, qw = Q.rule_degree5()
+    exact = 4.0 / 3.0 * np.pi * (1 - 0.55 ** 3)
+    errs = []
+    for level in range(4):
+        pr = O.Problem(v, t, level, O.P2V_EPSILON, O.BC_NONE, map_=O.MAP_SHELL_RADIAL, qbary=qb, qw=qw)
+        vol = 0.0
+        for m, tn, P, nodes in pr.element_batches():
+            s = np.sign(v[t[m]].mean(0))
+            J = el.blended_jacobians(P, s, qb)
+            vol += float(np.einsum("q,eq->", qw, np.abs(np.linalg.det(J))))
+        errs.append(abs(vol - exact))
+    rates = [np.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    print("volume errors", errs, "observed orders", rates)
+    assert errs[-1] <= 1e-7 * exact
+    assert min(rates[1:]) >= 5.0
