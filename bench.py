@@ -75,6 +75,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--main-only", action="store_true", help="skip the other forms")
     p.add_argument("--form-steps", type=int, default=20)
+    p.add_argument("--forms", default=None,
+                   help="comma-separated names of the forms to run (default: all), e.g. for profiler runs")
     p.add_argument("--copy-probe", action="store_true",
                    help="accepted for profiler runs: the 1 GiB device copy (a plain copy kernel of known "
                         "size, used to scale HBM byte counters) now always runs first")
@@ -227,10 +229,11 @@ def kernel_code_hash(sources=KERNEL_SOURCES, csrc=None):
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel_key, tile):
-    """HBM bytes per launch of one element-kernel tile shape, from the committed rocprofv3 counter runs
-    (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a 1 GiB copy); None when the kernel
-    code has changed since the counters were taken."""
+def traffic_for(kernel_key, tile, field="bytes_per_launch_by_tile"):
+    """HBM bytes per launch of one element-kernel tile shape (or, with field
+    "seam_bytes_per_launch_by_tile", of the seam reduction launched after it), from the committed
+    rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a 1 GiB copy);
+    None when the kernel code has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -239,7 +242,7 @@ def traffic_for(kernel_key, tile):
     ent = data.get(kernel_key)
     if not ent or kernel_code_hash(tuple(ent.get("sources", ()))) != ent.get("code_sha256_16"):
         return None
-    return ent["bytes_per_launch_by_tile"].get("x".join(str(v) for v in tile))
+    return ent.get(field, {}).get("x".join(str(v) for v in tile))
 
 
 def batched_solve(torch, T, W, hip, steps):
@@ -296,24 +299,80 @@ def batched_solve(torch, T, W, hip, steps):
     return res
 
 
-def cpu_baseline_c2():
-    """The oracle, as it stands, on one full apply of the headline workload (host cores)."""
+def host_cpu():
+    """Host CPU description from lscpu (model, sockets, cores per socket, threads per core)."""
+    import subprocess
+    try:
+        r = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20)
+    except (OSError, subprocess.SubprocessError):
+        return None
+    want = {"Model name": "model", "Socket(s)": "sockets", "Core(s) per socket": "cores_per_socket",
+            "Thread(s) per core": "threads_per_core", "CPU(s)": "logical_cpus"}
+    out = {}
+    for ln in r.stdout.splitlines():
+        k, _, v = ln.partition(":")
+        if k.strip() in want:
+            out[want[k.strip()]] = v.strip()
+    return out or None
+
+
+def usable_cores():
+    """Cores this process may run on (its affinity mask), at most 16: the CPU share of one GPU."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+_BASE = {}
+
+
+def _baseline_share(i):
+    """Worker: one share of the oracle's element loop, written into row i of the shared buffer."""
     from threadpoolctl import threadpool_limits
+    b = _BASE
+    with threadpool_limits(1):
+        b["out"][i, :] = b["pr"].local_sum(b["x"], b["k"], share=(i, b["nw"]))
+    return i
+
+
+def cpu_baseline_c2(reps=10):
+    """The oracle, as it stands, on full applies of the headline workload, its element loop split
+    over the host's cores.  Each worker process runs a share of the oracle's element batches
+    (single-threaded numpy); the parent adds the shares, then runs the oracle's interface sum and
+    mask.  Runs before anything touches the GPU: the workers are forked from this process."""
+    import mmap
+    import multiprocessing as mp
     import oracle as O
     import workloads as W
     v, t = W.meshes.kuhn_cube()
-    with threadpool_limits(1):
-        pr = O.Problem(v, t, 6, O.P2_DIVKGRAD, O.BC_DIRICHLET_ZERO)
-        x = W.uniform_from_keys(2, pr.keys)
-        k = W.fields.cube_k(pr.xyz)
-        n, t0 = 0, time.perf_counter()
-        while n == 0 or time.perf_counter() - t0 < 10.0:
-            pr.apply(x, k)
-            n += 1
-        dt = (time.perf_counter() - t0) / n
-    return {"value": pr.n_unique / dt / 1e6, "unit": "MDoF/s", "cores": 1, "kind": "oracle",
-            "sample": "%d full FP64 applies of the headline workload (Kuhn cube, level 6, %d DoFs), "
-                      "numpy oracle single-threaded, setup excluded; %.1f s per apply" % (n, pr.n_unique, dt)}
+    pr = O.Problem(v, t, 6, O.P2_DIVKGRAD, O.BC_DIRICHLET_ZERO)
+    x = W.uniform_from_keys(2, pr.keys)
+    k = W.fields.cube_k(pr.xyz)
+    nw = usable_cores()
+    buf = mmap.mmap(-1, nw * x.size * 8)  # anonymous shared memory, inherited by the forked workers
+    out = np.frombuffer(buf, dtype=np.float64).reshape(nw, x.size)
+    _BASE.update(pr=pr, x=x, k=k, nw=nw, out=out)
+    times = []
+    with mp.get_context("fork").Pool(nw) as pool:
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            pool.map(_baseline_share, range(nw))
+            y = pr.finish(out.sum(0))
+            times.append(time.perf_counter() - t0)
+    _BASE.clear()
+    del out
+    buf.close()
+    ref_norm = float(np.linalg.norm(y))
+    dt = float(np.median(times))
+    return {"value": pr.n_unique / dt / 1e6, "unit": "MDoF/s", "cores": nw, "kind": "oracle",
+            "host": host_cpu(), "reps": reps, "s_per_apply_median": round(dt, 4),
+            "s_per_apply_min": round(float(np.min(times)), 4), "y_norm": ref_norm,
+            "sample": "%d full FP64 applies of the headline workload (Kuhn cube, level 6, %d DoFs) by the numpy "
+                      "oracle, its element batches split over %d single-threaded worker processes, shares added "
+                      "and finished (interface sum, mask) in the parent; setup excluded; median %.2f s per apply"
+                      % (reps, pr.n_unique, nw, dt)}
 
 
 def main():
@@ -323,6 +382,12 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path (sharding by "
               "macro-tetrahedra is described in DESIGN.md); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    cpu_base = None
+    if not args.no_cpu_baseline:
+        # first, while no GPU handle exists in this process (its workers are forked)
+        log("cpu baseline (oracle) ...")
+        cpu_base = cpu_baseline_c2()
+        log("cpu baseline %.3f MDoF/s on %d cores" % (cpu_base["value"], cpu_base["cores"]))
     import torch
     import paper_2404_08371_amd as T
     import workloads as W
@@ -395,7 +460,9 @@ def main():
         achieved, peak, unit = flops / (kern * 1e-3) / 1e12, PEAK_FP64 / 1e12, "TFLOP/s"
     else:
         achieved, peak, unit = bytes_alg / (kern * 1e-3) / 1e9, PEAK_HBM / 1e9, "GB/s"
-    traffic = traffic_for("p2_divkgrad_fp64_cube6", (tx.value, ty.value, tz.value))
+    tile = (tx.value, ty.value, tz.value)
+    traffic = traffic_for("p2_divkgrad_fp64_cube6", tile)
+    seam_traffic = traffic_for("p2_divkgrad_fp64_cube6", tile, "seam_bytes_per_launch_by_tile")
     value = op.n_unique / (wall * 1e-3) / 1e6
     out = {
         "metric": "operator-apply MDoF/s (FP64 vs FP32-refined, fwd+adjoint) and % HBM roofline",
@@ -411,6 +478,12 @@ def main():
                      "kernel_ms": round(kern, 5), "flops_per_launch": flops,
                      "alg_bytes_per_launch": bytes_alg,
                      "hbm_frac": round(bytes_alg / (kern * 1e-3) / PEAK_HBM, 4),
+                     # the whole apply (element kernel and seam / interface reduction), timed as the
+                     # step: its algorithmic bytes over the step time, and its measured HBM bytes
+                     "step_ms": round(wall, 5),
+                     "step_hbm_frac": round(bytes_alg / (wall * 1e-3) / PEAK_HBM, 4),
+                     "step_traffic": (traffic + seam_traffic) if traffic is not None and seam_traffic is not None
+                     else None,
                      "device_copy_GBps": round(copy_gbs, 1), **kstats},
         "clocks": clock_state(),
     }
@@ -420,8 +493,15 @@ def main():
     if not args.main_only:
         forms = {}
 
+        sel = None if args.forms is None else set(args.forms.split(","))
+
+        def want(name):
+            return sel is None or name in sel
+
         def form(name, mesh, op, fam, seed, flops_launch, bytes_launch, peak_flops, steps, adjoint=False,
                  dofs=None):
+            if not want(name):
+                return
             xx, kk = device_inputs(mesh, op, seed, torch, fam)
             yy = torch.empty_like(xx)
             if op.space == 2:
@@ -493,30 +573,34 @@ def main():
         del oq
         # stored local matrices (the precomputed-matrix comparison) on the headline workload:
         # 55 FP64 entries per micro-tet streamed from HBM, plus x and y
-        ost = T.Operator(mesh, T.P2_DIVKGRAD, T.F64)
-        xs_, ks_ = device_inputs(mesh, ost, 2, torch, "p2_divkgrad")
-        ost.store_matrices(ks_)
-        ys_ = torch.empty_like(xs_)
-        Ls = T.lib()
-        sts = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        def stored_form():
+            ost = T.Operator(mesh, T.P2_DIVKGRAD, T.F64)
+            xs_, ks_ = device_inputs(mesh, ost, 2, torch, "p2_divkgrad")
+            ost.store_matrices(ks_)
+            ys_ = torch.empty_like(xs_)
+            Ls = T.lib()
+            sts = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
-        def fn_stored(b, a):
-            if b is not None:
-                hip.L.hipEventRecord(b, sts)
-            T.check(Ls.tmf_apply_stored(ost.handle, ctypes.c_void_p(xs_.data_ptr()), ctypes.c_void_p(ys_.data_ptr()),
-                                        sts))
-            if a is not None:
-                hip.L.hipEventRecord(a, sts)
-        w_s, k_s = time_apply(ost, xs_, ks_, ys_, args.form_steps, 3, hip, torch, fn_stored)
-        b_s = 55 * 8 * nel + 16 * ost.n_local
-        forms["p2_divkgrad_stored_matrices_fp64_cube_l6"] = {
-            "dofs": ost.n_unique, "mdofs": round(ost.n_unique / (w_s * 1e-3) / 1e6, 2), "ms_per_apply": round(w_s, 5),
-            "kernel_ms": round(k_s, 5), "stored_bytes": 55 * 8 * nel,
-            "hbm_frac": round(b_s / (k_s * 1e-3) / PEAK_HBM, 4),
-            "alu_frac": round(nel * FLOPS["p2_stored"] / (k_s * 1e-3) / PEAK_FP64, 4),
-            "matrix_free_speedup": round(w_s / wall, 2)}
-        log("p2_divkgrad_stored_matrices_fp64_cube_l6", forms["p2_divkgrad_stored_matrices_fp64_cube_l6"])
-        del ost, xs_, ks_, ys_
+            def fn_stored(b, a):
+                if b is not None:
+                    hip.L.hipEventRecord(b, sts)
+                T.check(Ls.tmf_apply_stored(ost.handle, ctypes.c_void_p(xs_.data_ptr()), ctypes.c_void_p(ys_.data_ptr()),
+                                            sts))
+                if a is not None:
+                    hip.L.hipEventRecord(a, sts)
+            w_s, k_s = time_apply(ost, xs_, ks_, ys_, args.form_steps, 3, hip, torch, fn_stored)
+            b_s = 55 * 8 * nel + 16 * ost.n_local
+            forms["p2_divkgrad_stored_matrices_fp64_cube_l6"] = {
+                "dofs": ost.n_unique, "mdofs": round(ost.n_unique / (w_s * 1e-3) / 1e6, 2), "ms_per_apply": round(w_s, 5),
+                "kernel_ms": round(k_s, 5), "stored_bytes": 55 * 8 * nel,
+                "hbm_frac": round(b_s / (k_s * 1e-3) / PEAK_HBM, 4),
+                "alu_frac": round(nel * FLOPS["p2_stored"] / (k_s * 1e-3) / PEAK_FP64, 4),
+                "matrix_free_speedup": round(w_s / wall, 2)}
+            log("p2_divkgrad_stored_matrices_fp64_cube_l6", forms["p2_divkgrad_stored_matrices_fp64_cube_l6"])
+            del ost, xs_, ks_, ys_
+
+        if want("p2_divkgrad_stored_matrices_fp64_cube_l6"):
+            stored_form()
         # P2 adjoint (gx = L(k) gy and gk), two element launches + two seam reductions;
         # 48 B per slot (gy, k -> gx; x, gy -> gk)
         o6a = T.Operator(mesh, T.P2_DIVKGRAD, T.F64)
@@ -539,14 +623,14 @@ def main():
                      adjoint=True)
             del oe
         # batched mixed-precision solve: 32 reference-tet instances, levels in {3..7}
-        log("batched FP32-in-FP64 refinement, 32 instances")
-        forms["batched_ir_cg_p2_divkgrad_32x"] = batched_solve(torch, T, W, hip, args.form_steps)
-        log("batched_ir_cg_p2_divkgrad_32x", forms["batched_ir_cg_p2_divkgrad_32x"])
+        if want("batched_ir_cg_p2_divkgrad_32x"):
+            log("batched FP32-in-FP64 refinement, 32 instances")
+            forms["batched_ir_cg_p2_divkgrad_32x"] = batched_solve(torch, T, W, hip, args.form_steps)
+            log("batched_ir_cg_p2_divkgrad_32x", forms["batched_ir_cg_p2_divkgrad_32x"])
         out["forms"] = forms
 
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline_c2()
+    if cpu_base is not None:
+        out["cpu_baseline"] = cpu_base
     print(json.dumps(out), flush=True)
 
 

@@ -195,13 +195,21 @@ class Problem:
     # ------------------------------------------------------------- apply
     def apply(self, x, coeff=None, rows=None):
         """y = A x.  With `rows` (local indices), only y at those rows (and their copies) is exact."""
+        return self.finish(self.local_sum(x, coeff, rows=rows))
+
+    def local_sum(self, x, coeff=None, rows=None, share=(0, 1)):
+        """The element loop of the apply: sum over micro-tets T of P_T A_T R_T (D x), before the
+        interface sum and the output mask.  `share` = (i, n) restricts it to the element batches
+        whose index is i modulo n (the n shares add up to the whole loop)."""
         x, coeff = self._check(x, coeff)
         xm = self._mask(x)
         y = np.zeros_like(x)
         need = None
         if rows is not None:
             need = np.isin(self.uid, np.unique(self.uid[np.asarray(rows)]))
-        for m, tn, P, nodes in self.element_batches():
+        for j, (m, tn, P, nodes) in enumerate(self.element_batches()):
+            if j % share[1] != share[0]:
+                continue
             if need is not None:
                 sel = need[nodes].any(1)
                 if not sel.any():
@@ -211,6 +219,10 @@ class Problem:
             idx = self._dof_index(nodes)
             ye = np.einsum("eji,ei->ej", A, xm[idx])
             y += np.bincount(idx.ravel(), weights=ye.ravel(), minlength=y.size)
+        return y
+
+    def finish(self, y):
+        """Interface sum over the copies of each DoF, then the output mask D."""
         return self._mask(self.interface_sum(y))
 
     # ---------------------------------------------------------- diagonal

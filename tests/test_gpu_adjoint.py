@@ -116,7 +116,7 @@ def test_adjoint_fp32_matches_fp64():
                               torch.tensor(x, device="cuda", dtype=torch.float32), gy.float())
     for a64, a32 in ((gx64, gx32), (gk64, gk32)):
         a64, a32 = a64.cpu().numpy(), a32.double().cpu().numpy()
-        assert np.abs(a64 - a32).max() <= 2e-5 * np.abs(a64).max()
+        assert np.abs(a64 - a32).max() <= 1e-5 * np.abs(a64).max()
 
 
 def test_backward_is_the_transpose_of_the_forward_map():
@@ -211,7 +211,7 @@ def test_p2_adjoint_fp32_matches_fp64():
                               torch.tensor(x, device="cuda", dtype=torch.float32), gy.float())
     for a64, a32 in ((gx64, gx32), (gk64, gk32)):
         a64, a32 = a64.cpu().numpy(), a32.double().cpu().numpy()
-        assert np.abs(a64 - a32).max() <= 2e-5 * np.abs(a64).max()
+        assert np.abs(a64 - a32).max() <= 1e-5 * np.abs(a64).max()
 
 
 def test_p2_coefficient_gradient_is_the_linear_part():
@@ -242,9 +242,11 @@ def eps_problem(mesh, level, prec=T.F64):
     return m, op, info, mu, x, b
 
 
-@pytest.mark.parametrize("mesh,level", [("flatshell", 2), ("shell", 1)])
+@pytest.mark.parametrize("mesh,level", [("flatshell", 2), ("shell", 1), ("flatshell", 3), ("shell", 3)])
 def test_eps_gradients_match_oracle(mesh, level):
-    """Affine and radially blended epsilon operator: dL/dx and dL/dmu against the oracle (FP64, 1e-12)."""
+    """Affine and radially blended epsilon operator: dL/dx and dL/dmu against the oracle (FP64, 1e-12).
+    At level 3 a macro spans four 4 x 4 x 4 tile boxes, so both gradients pass through the
+    seam reduction of neighbouring tiles' partial sums."""
     from helpers import inputs, oracle_problem
     print("eps adjoint case", mesh, level, flush=True)
     m, op, info, mu, x, b = eps_problem(mesh, level)
@@ -271,8 +273,10 @@ def test_eps_gradients_match_oracle(mesh, level):
     assert np.linalg.norm(tm - gmu) <= 1e-12 * np.linalg.norm(gmu)
 
 
-def test_eps_adjoint_fp32_matches_fp64():
-    m, op, info, mu, x, b = eps_problem("shell", 2)
+@pytest.mark.parametrize("level", [2, 3])
+def test_eps_adjoint_fp32_matches_fp64(level):
+    print("eps adjoint fp32 case", level, flush=True)
+    m, op, info, mu, x, b = eps_problem("shell", level)
     op32 = T.Operator(m, T.P2V_EPSILON, T.F32, T.BC_DIRICHLET_ZERO, rule=W.quadrature.rule_degree5())
     gy = torch.tensor(b, device="cuda")
     gx64, gm64 = op.adjoint(torch.tensor(mu, device="cuda"), torch.tensor(x, device="cuda"), gy)
@@ -280,4 +284,4 @@ def test_eps_adjoint_fp32_matches_fp64():
                               torch.tensor(x, device="cuda", dtype=torch.float32), gy.float())
     for a64, a32 in ((gx64, gx32), (gm64, gm32)):
         a64, a32 = a64.cpu().numpy(), a32.double().cpu().numpy()
-        assert np.abs(a64 - a32).max() <= 2e-5 * np.abs(a64).max()
+        assert np.abs(a64 - a32).max() <= 1e-5 * np.abs(a64).max()

@@ -114,7 +114,7 @@ def test_epsilon_shell_level6_sampled_rows(shell6, prec):
     scale = np.abs(ref[idx]).max()
     err = np.abs(y[idx] - ref[idx]).max() / scale
     print("C3 sampled max rel err", err)
-    assert err <= (1e-12 if prec == T.F64 else 2e-5)
+    assert err <= (1e-12 if prec == T.F64 else 1e-5)
 
 
 def test_epsilon_shell_level6_constants_in_kernel(shell6):
@@ -141,9 +141,22 @@ def test_p1_laplace_level9_properties():
     r = torch.rand(opn.n_local, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(0))
     scale = opn.apply(r).abs().max().item()
     assert opn.apply(ones).abs().max().item() <= 1e-12 * scale
-    # the linear field is evaluated on the host (a device matvec of this 22.6M x 3
-    # position array through torch returned wrong values on the test machine)
-    lin = torch.tensor(info["xyz"] @ np.array([0.3, -1.1, 2.0]) + 0.5, device="cuda")
+    # The linear field is built on the device, with no host copy between it and
+    # the apply (so stream ordering is exercised), by elementwise products; it is
+    # checked against the host's evaluation first.  torch's matrix-vector product
+    # of the 22.6M x 3 position array is evaluated too and its deviation printed:
+    # it returned wrong values on the test machine once, so it is not used.
+    v3 = np.array([0.3, -1.1, 2.0])
+    lin_h = info["xyz"] @ v3 + 0.5
+    xyz_t = torch.tensor(info["xyz"], device="cuda")
+    v3_t = torch.tensor(v3, device="cuda")
+    lin = (xyz_t[:, 0] * v3_t[0] + xyz_t[:, 1] * v3_t[1]) + (xyz_t[:, 2] * v3_t[2] + 0.5)
+    lin_mm = xyz_t @ v3_t + 0.5
+    dev_ew = np.abs(lin.cpu().numpy() - lin_h).max()
+    dev_mm = np.abs(lin_mm.cpu().numpy() - lin_h).max()
+    print("linear field: device elementwise vs host %.3e, torch matvec vs host %.3e" % (dev_ew, dev_mm))
+    del lin_mm, xyz_t
+    assert dev_ew <= 1e-14
     y = opn.apply(lin)
     interior = torch.tensor(~info["boundary"], device="cuda")
     assert y[interior].abs().max().item() <= 1e-12 * scale

@@ -4,7 +4,7 @@ Tolerances: FP64 relative error (2-norm and max-norm, relative to the
 oracle's norms) <= 1e-12, the bound the target states for FP64.  FP32 applies
 evaluate the same formulas with 24-bit mantissas; with O(100) accumulated
 terms per output the expected relative error is ~1e-6, and the bound used is
-2e-5 relative to the max-norm of y.
+1e-5 relative to the max-norm of y.
 """
 import sys
 
@@ -57,8 +57,10 @@ for kind in (O.P1_LAPLACE, O.P1_DIVKGRAD):
 for kind in (O.P2_LAPLACE, O.P2_DIVKGRAD):
     CASES += [("ref", l, kind) for l in (0, 1, 2, 3, 4)] + [("cube", l, kind) for l in (0, 1, 3)]
     CASES += [("flatshell", 1, kind)]
-CASES += [("cube", l, O.P2V_EPSILON) for l in (0, 1, 2)] + [("flatshell", 1, O.P2V_EPSILON)]
-CASES += [("shell", l, O.P2V_EPSILON) for l in (0, 1)]
+# epsilon: levels 3 and 4 hold several 4 x 4 x 4 tile boxes per macro, so the
+# seam reduction adds partial sums of neighbouring tiles
+CASES += [("cube", l, O.P2V_EPSILON) for l in (0, 1, 2, 3, 4)] + [("flatshell", l, O.P2V_EPSILON) for l in (1, 3)]
+CASES += [("shell", l, O.P2V_EPSILON) for l in (0, 1, 2, 3)]
 
 
 @pytest.mark.parametrize("bc", [O.BC_DIRICHLET_ZERO, O.BC_NONE])
@@ -72,7 +74,7 @@ def test_fp64_parity(mesh, level, kind, bc):
 def test_fp32_parity(mesh, level, kind):
     e2, ei = run_case(mesh, level, kind, O.BC_DIRICHLET_ZERO, T.F32)
     print("fp32 rel err", e2, ei)
-    assert ei <= 2e-5, (e2, ei)
+    assert ei <= 1e-5, (e2, ei)
 
 
 @pytest.mark.parametrize("cfg", [0, 1, 2, 3])
@@ -90,7 +92,7 @@ def test_every_tile_shape(cfg, kind, prec):
     y = op.apply(torch.tensor(x, dtype=dt, device="cuda"),
                  torch.tensor(k, dtype=dt, device="cuda") if k is not None else None)
     e2, ei = rel_err(y.double().cpu().numpy(), pr.apply(x, k))
-    assert ei <= (1e-12 if prec == T.F64 else 2e-5), (e2, ei)
+    assert ei <= (1e-12 if prec == T.F64 else 1e-5), (e2, ei)
 
 
 @pytest.mark.parametrize("mesh,level,kind", [("cube", 3, O.P2_DIVKGRAD), ("cube", 4, O.P2_LAPLACE),

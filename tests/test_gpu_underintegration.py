@@ -1,6 +1,6 @@
 """GPU quadrature variant of P2 div(k grad) (the under-integration option:
 weights from a degree-2 rule) against the oracle's quadrature element, FP64
-<= 1e-12 and FP32 <= 2e-5 relative max-norm; with a degree-5 rule the variant
+<= 1e-12 and FP32 <= 1e-5 relative max-norm; with a degree-5 rule the variant
 equals the exactly integrated GPU operator (the integrand has degree 4).
 Operations defined for the exact operator only refuse the variant."""
 import ctypes
@@ -41,7 +41,7 @@ def test_degree2_variant_matches_oracle(level, bc, prec):
     pr = O.Problem(v, t, level, O.P2_DIVKGRAD, bc, qbary=rule[0], qw=rule[1])
     ref = pr.apply(W.uniform_from_keys(6, pr.keys), W.fields.cube_k(pr.xyz))
     e2, ei = rel_err(y, ref)
-    assert ei <= (1e-12 if prec == T.F64 else 2e-5), (e2, ei)
+    assert ei <= (1e-12 if prec == T.F64 else 1e-5), (e2, ei)
 
 
 def test_degree5_variant_equals_exact_operator():

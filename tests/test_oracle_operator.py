@@ -273,3 +273,15 @@ def test_cg_matches_sparse_direct_solve():
     xd = np.zeros(pr.n_unique)
     xd[inner] = spla.spsolve(A[inner][:, inner].tocsc(), pr.to_unique(b)[inner])
     assert np.allclose(pr.to_unique(x), xd, rtol=1e-10, atol=1e-10 * np.abs(xd).max())
+
+
+def test_local_sum_shares_add_up_to_the_apply():
+    """The element loop split into shares (as the CPU baseline splits it over worker
+    processes) adds up to the apply, up to summation order."""
+    v, t = W.meshes.kuhn_cube()
+    pr = O.Problem(v, t, 2, O.P2_DIVKGRAD, O.BC_DIRICHLET_ZERO)
+    x = W.uniform_from_keys(2, pr.keys)
+    k = W.fields.cube_k(pr.xyz)
+    ref = pr.apply(x, k)
+    y = pr.finish(sum(pr.local_sum(x, k, share=(i, 5)) for i in range(5)))
+    assert np.abs(y - ref).max() <= 1e-14 * np.abs(ref).max()
