@@ -25,6 +25,7 @@ struct tmf_batch {
   DevBuf<int4> tiles[kNumTileCfg];
   int ntiles[kNumTileCfg] = {0};
   int tile_cfg = 0;
+  int classic_cfg = 0;  // box shape for the diagonal mode when tile_cfg is a marching shape
   // reduction chunks over the concatenated vectors
   DevBuf<ChunkDesc> chunks;
   int nchunks = 0;
@@ -69,10 +70,11 @@ hipError_t batch_apply_t(tmf_batch *b, int mode, const void *coeff, const void *
   hipError_t e = hipSuccess;
   if (active && zero_inactive) e = launch_fill<T>(yy, b->off[b->count], T(0), s);
   if (e != hipSuccess) return e;
+  const int c = mode_cfg(b->tile_cfg, b->classic_cfg, mode);
   TileArgs<T> a;
   a.inst = reinterpret_cast<const InstDesc<T> *>(b->desc.p);
-  a.tiles = b->tiles[b->tile_cfg].p;
-  a.ntiles = b->ntiles[b->tile_cfg];
+  a.tiles = b->tiles[c].p;
+  a.ntiles = b->ntiles[c];
   a.active = active;
   a.qtab = nullptr;
   a.nq = 0;
@@ -80,14 +82,16 @@ hipError_t batch_apply_t(tmf_batch *b, int mode, const void *coeff, const void *
   a.x = static_cast<const T *>(x);
   a.y = yy;
   if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
-  e = launch_tile_apply<T>(a, mode, TMF_MAP_AFFINE, b->tile_cfg, s);
+  e = launch_tile_apply<T>(a, mode, TMF_MAP_AFFINE, c, s);
   if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
   if (e != hipSuccess) return e;
   // seam and interface reduction of every instance, one launch
-  const int c = b->tile_cfg;
   return launch_seam_gather<T>(reinterpret_cast<const SeamInst<T> *>(b->seaminst[c].p), b->seamwork[c].p,
                                b->nseamwork[c], yy, active, 0, b->ncomp, seam_ppt(b->ops[0]), c, b->seamrows[c], s);
 }
+
+// tile shapes of a batch: epsilon has one; the scalar P2 kinds also take the marching shapes
+int batch_num_tiles(const tmf_batch *b) { return b->kind == TMF_P2V_EPSILON ? 1 : kNumTileCfg; }
 
 tmf_status batch_apply(tmf_batch *b, const void *coeff, const void *x, void *y, const uint8_t *active,
                        hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool zero_inactive = true) {
@@ -269,9 +273,9 @@ tmf_status tmf_batch_diagonal(tmf_batch *b, const void *coeff, void *d, tmf_stre
 
 tmf_status tmf_batch_set_tile(tmf_batch *b, int cfg) {
   if (!b) return fail(TMF_EINVAL, "batch is NULL");
-  const int nt = b->kind == TMF_P2V_EPSILON ? 1 : kNumTileCfg;
-  if (cfg < 0 || cfg >= nt) return fail(TMF_EINVAL, "tile shape %d out of range", cfg);
+  if (cfg < 0 || cfg >= batch_num_tiles(b)) return fail(TMF_EINVAL, "tile shape %d out of range", cfg);
   b->tile_cfg = cfg;
+  if (kTileMarch[cfg] == 0) b->classic_cfg = cfg;
   return TMF_OK;
 }
 
@@ -288,9 +292,9 @@ tmf_status tmf_batch_autotune(tmf_batch *b, const void *coeff, const void *x, vo
     return fail(TMF_EDEVICE, "hipEventCreate failed");
   }
   const int keep = b->tile_cfg;
-  int best = keep;
-  float best_t = 0;
-  const int nt = b->kind == TMF_P2V_EPSILON ? 1 : kNumTileCfg;
+  int best = keep, best_box = b->classic_cfg;
+  float best_t = 0, best_box_t = 0;
+  const int nt = batch_num_tiles(b);
   for (int cfg = 0; cfg < nt && st == TMF_OK; ++cfg) {
     b->tile_cfg = cfg;
     for (int w = 0; w < 2 && st == TMF_OK; ++w) st = batch_apply(b, coeff, x, y, nullptr, s);
@@ -307,10 +311,15 @@ tmf_status tmf_batch_autotune(tmf_batch *b, const void *coeff, const void *x, vo
       best_t = ms;
       best = cfg;
     }
+    if (st == TMF_OK && kTileMarch[cfg] == 0 && (cfg == 0 || ms < best_box_t)) {
+      best_box_t = ms;
+      best_box = cfg;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   b->tile_cfg = st == TMF_OK ? best : keep;
+  if (st == TMF_OK) b->classic_cfg = best_box;
   if (st != TMF_OK) return st;
   if (best_cfg) *best_cfg = best;
   if (best_ms) *best_ms = best_t;

@@ -684,7 +684,7 @@ hipError_t tile_path(tmf_op *op, int kind, const void *coeff, const void *x, T *
                      hipEvent_t ev1, bool interface, const void *x2 = nullptr, int seam_flags = 0,
                      int ncomp_out = 0, void *mat = nullptr, int cfg = -1, bool gather = true) {
   hipError_t e;
-  const int c = cfg >= 0 ? cfg : op->tile_cfg;
+  const int c = cfg >= 0 ? cfg : mode_cfg(op->tile_cfg, op->classic_cfg, kind);
   TileArgs<T> a;
   a.inst = reinterpret_cast<const InstDesc<T> *>(op->desc.p);
   a.tiles = op->tiles[c].p;
@@ -818,7 +818,7 @@ tmf_status tmf_op_store_matrices(tmf_op *op, const void *coeff, tmf_stream strea
   if (!op || !coeff) return fail(TMF_EINVAL, "op or coeff is NULL");
   if (op->kind != TMF_P2_DIVKGRAD || op->nq > 0)
     return fail(TMF_EUNSUPPORTED, "stored local matrices are provided for the exact TMF_P2_DIVKGRAD");
-  const int cfg = op->tile_cfg;
+  const int cfg = mode_cfg(op->tile_cfg, op->classic_cfg, P2_DIVKGRAD_STORE);
   const size_t esz = op->prec == TMF_F64 ? 8 : 4;
   const size_t cubes = static_cast<size_t>(kTileCfg[cfg][0]) * kTileCfg[cfg][1] * kTileCfg[cfg][2];
   const size_t bytes = static_cast<size_t>(op->ntiles[cfg]) * 6 * kStoredEntries * cubes * esz;
@@ -866,7 +866,10 @@ tmf_status tmf_interface_sum(tmf_op *op, void *v, tmf_stream stream) {
 
 static int num_tiles(const tmf_op *op) {
   if (op->space == 1) return 1;
-  return op->kind == TMF_P2V_EPSILON ? 1 : kNumTileCfg;
+  if (op->kind == TMF_P2V_EPSILON) return 1;
+  // the marching shapes serve the exactly integrated scalar P2 applies
+  const bool march = (op->kind == TMF_P2_LAPLACE || op->kind == TMF_P2_DIVKGRAD) && op->nq == 0;
+  return march ? kNumTileCfg : kNumClassicTileCfg;
 }
 
 tmf_status tmf_op_num_tiles(const tmf_op *op, int *count) {
@@ -888,6 +891,7 @@ tmf_status tmf_op_set_tile(tmf_op *op, int cfg) {
   if (!op) return fail(TMF_EINVAL, "op is NULL");
   if (cfg < 0 || cfg >= num_tiles(op)) return fail(TMF_EINVAL, "tile shape %d out of range", cfg);
   op->tile_cfg = cfg;
+  if (kTileMarch[cfg] == 0) op->classic_cfg = cfg;
   return TMF_OK;
 }
 
@@ -909,8 +913,8 @@ tmf_status tmf_op_autotune(tmf_op *op, const void *coeff, const void *x, void *y
     (void)hipEventDestroy(e0);
     return fail(TMF_EDEVICE, "hipEventCreate failed");
   }
-  int best = op->tile_cfg;
-  float best_t = 0;
+  int best = op->tile_cfg, best_box = op->classic_cfg;
+  float best_t = 0, best_box_t = 0;
   const int keep = op->tile_cfg;
   for (int cfg = 0; cfg < num_tiles(op) && st == TMF_OK; ++cfg) {
     op->tile_cfg = cfg;
@@ -928,6 +932,10 @@ tmf_status tmf_op_autotune(tmf_op *op, const void *coeff, const void *x, void *y
       best_t = ms;
       best = cfg;
     }
+    if (st == TMF_OK && kTileMarch[cfg] == 0 && (cfg == 0 || ms < best_box_t)) {
+      best_box_t = ms;
+      best_box = cfg;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -936,6 +944,7 @@ tmf_status tmf_op_autotune(tmf_op *op, const void *coeff, const void *x, void *y
     return st;
   }
   op->tile_cfg = best;
+  op->classic_cfg = best_box;
   if (best_cfg) *best_cfg = best;
   if (best_ms) *best_ms = best_t;
   return TMF_OK;

@@ -75,6 +75,7 @@ struct tmf_op {
   int kind = 0, prec = 0, bc = 0, space = 1, ncomp = 1, N = 1, nq = 0;
   int64_t L = 0, n_local = 0, n_unique = 0;
   int tile_cfg = 0;
+  int classic_cfg = 0;  // box shape for the modes the marching kernel does not provide
   DevBuf<uint8_t> geo, w15, mgeo, qtab;
   DevBuf<uint32_t> bnd;
   DevBuf<int4> tiles[kNumTileCfg];
@@ -101,6 +102,14 @@ struct tmf_op {
   int mat_cfg = -1;                       // tile shape they were stored for (-1: none)
   int seamrows[kNumTileCfg] = {0};        // tile-row table entries per macro, per tile shape
 };
+
+// tile shape of an element-kernel launch: the chosen shape, or the chosen box
+// shape when the chosen one is a marching shape and the mode is not a plain
+// scalar P2 apply
+inline int mode_cfg(int cfg, int box_cfg, int mode) {
+  const bool plain = mode == TMF_P2_LAPLACE || mode == TMF_P2_DIVKGRAD;
+  return (kTileMarch[cfg] != 0 && !plain) ? box_cfg : cfg;
+}
 
 // seam-reduction descriptor of an op with tile shape `cfg` at offset `yoff`
 template <typename T>

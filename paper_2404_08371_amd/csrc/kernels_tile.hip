@@ -1337,6 +1337,379 @@ __global__ __launch_bounds__(256, 5) void k_seam(const SeamInst<T> *__restrict__
     body(gptr(a.rowstart));
 }
 
+// ---------------------------------------------------------------------------
+// Marching element kernel for the scalar P2 applies (P2_LAPLACE, P2_DIVKGRAD).
+//
+// A tile here is a column segment of S sub-boxes of 4 x 4 x 4 micro-cubes
+// stacked in z (the cubes loop of section "Cubes Loop Strategy", marched
+// along z).  The launch is persistent: each workgroup walks its share of the
+// segments sub-box by sub-box and
+//   - stages the next sub-box's x (Dirichlet DoFs as 0) and coefficient
+//     straight from HBM into a second LDS buffer with buffer-to-LDS loads
+//     (no registers held) while it applies the current one, so the load
+//     latency of one sub-box hides behind the element work of the previous;
+//   - carries the partial sums of the face shared by two sub-boxes of a
+//     segment in LDS: that face is written once, complete, by the upper
+//     sub-box, never through HBM;
+//   - writes the points of the segment's own faces shared with neighbouring
+//     segments as partial sums, in the segment-box layout the seam reduction
+//     reads (the seam reduction treats a segment as one tall box).
+// Per sub-box: the loads of the next sub-box are issued, the micro-tets are
+// applied (wavefront w: types w and w + 3, a lane per cube, LDS atomics into
+// the accumulator), then the sub-box is written back, the accumulator is
+// cleared (keeping the carried face), and the tables of the sub-box after
+// next are built.  Three LDS barriers; the only wait on global memory follows
+// the element work, for the loads issued before it (the write-back's stores
+// drain during the next sub-box).
+
+// LDS barrier without a wait on global memory (buffer-to-LDS loads and
+// global stores stay in flight): the fences order LDS accesses only
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+// wait for this wavefront's vector memory operations (vmcnt(0); LDS counter untouched)
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+template <typename T, int KIND, int S>
+struct MarchCfg {
+  static constexpr int TX = 4, TY = 4, TZS = 4;     // sub-box, micro-cubes
+  static constexpr int RX = 9, RY = 9, RZ = 9;      // sub-box lattice points
+  static constexpr int OO = TX + 1, RXP = 10;       // LDS row: even points, odd points, pitch (as TileCfg)
+  static constexpr int ROWS = RY * RZ;
+  static constexpr int RP = RXP * ROWS;             // LDS slots of one staged array
+  static constexpr int PLANE = RXP * RY;            // LDS slots of one lattice plane
+  static constexpr int DW = sizeof(T) / 4;          // dwords per value
+  // each staged array is padded to whole 64-dword loads, so that every
+  // buffer-to-LDS load belongs to one array (its buffer descriptor is uniform)
+  static constexpr int RPA = ((RP * DW + 63) / 64) * 64 / DW;
+  static constexpr int IPA = RPA * DW / 64;         // loads per array per sub-box
+  static constexpr bool HASK = KIND == P2_DIVKGRAD;
+  static constexpr int NA = HASK ? 2 : 1;
+  static constexpr int NINS = NA * IPA;
+  static constexpr int WPG = 3, NTH = 64 * WPG;
+  static constexpr int IPW = (NINS + WPG - 1) / WPG;  // loads per wavefront
+  static constexpr int TZ = TZS * S;                 // segment height in cubes
+  static constexpr int RSEG = RX * RY * (2 * TZ + 1);  // points of the segment box (partial layout)
+};
+
+// one sub-box of the march: segment (tile index), sub-box in the segment
+struct MarchItem {
+  int seg, sub;
+};
+
+// descriptors read through the constant address space (scalar loads)
+template <typename T>
+using CDesc = const __attribute__((address_space(4))) InstDesc<T>;
+// tile record i of a list, read through the constant address space
+__device__ __forceinline__ int4 tile_rec(const int4 *tiles, int i) {
+  const CPtr<int> q = cptr(reinterpret_cast<const int *>(tiles)) + 4 * i;
+  return make_int4(q[0], q[1], q[2], q[3]);
+}
+// row table entry (.x, .y) from LDS as one 64-bit read
+__device__ __forceinline__ int2 row_rec(LPtr<uint64_t> t, int row) {
+  const uint64_t v = t[row];
+  return make_int2(static_cast<int>(static_cast<uint32_t>(v)), static_cast<int>(static_cast<uint32_t>(v >> 32)));
+}
+
+// Row table entry of a sub-box, one per lattice row (ry, rz):
+//   .x = macro-block index of the row's point at rx = 0
+//   .y = bits 0-8: rx whose x is staged (inside the macro, not a Dirichlet
+//        DoF); bits 9-17: rx inside the macro (coefficient staged, point
+//        written back); bit 18: the row's last macro point qi = lim lies in the
+//        box; 19: qj = 0; 20: qk = 0; 21: the row's points belong to this
+//        segment in y and z (write-back); bits 24-28: largest rx inside the macro
+template <typename T, int KIND, int S>
+__device__ __forceinline__ void march_row_table(CDesc<T> *D, int4 tl, int sub, int row, int2 *trow) {
+  using C = MarchCfg<T, KIND, S>;
+  const int m = tl.y;
+  const int bx0 = tl.z & 1023, by0 = (tl.z >> 10) & 1023, bz0 = (tl.z >> 20) & 1023;
+  const int N = D->N;
+  const int ry = row % C::RY, rz = row / C::RY;
+  const int qj = 2 * by0 + ry, qk = 2 * (bz0 + C::TZS * sub) + rz;
+  const int lim = N - qj - qk, L = lim - 2 * bx0;
+  const bool empty = L < 0;
+  const int khi = empty ? 0 : min(L, 2 * C::TX);
+  const bool limin = !empty && L <= 2 * C::TX;
+  const int rowzp = ((qj == 0) << 2) | ((qk == 0) << 3);
+  const uint32_t kmask = empty ? 0u : (2u << khi) - 1u;
+  uint32_t xmask = kmask;
+  if (D->dirichlet && !empty) {
+    const uint32_t bnd = *cptr(D->bnd + m);
+    if ((bnd >> rowzp) & 1u) xmask = 0u;
+    if (bx0 == 0 && ((bnd >> (rowzp | 2 | (lim == 0 ? 1 : 0))) & 1u)) xmask &= ~1u;
+    if (limin && ((bnd >> (rowzp | 1 | (lim == 0 ? 2 : 0))) & 1u)) xmask &= ~(1u << khi);
+  }
+  const int rzs = 2 * C::TZS * sub + rz;  // plane within the segment box
+  const bool ey = (ry & 1) || ((ry > 0 || by0 == 0) && ry < 2 * C::TY);
+  const bool ez = (rzs & 1) || ((rzs > 0 || bz0 == 0) && rzs < 2 * C::TZ);
+  trow[row] = make_int2(empty ? 0 : row_base(qj, qk, N) + 2 * bx0,
+                        static_cast<int>(xmask | (kmask << 9) | (uint32_t(limin) << 18) | (uint32_t(qj == 0) << 19) |
+                                         (uint32_t(qk == 0) << 20) | (uint32_t(ey && ez) << 21) |
+                                         (uint32_t(khi) << 24)));
+}
+
+// issue this wavefront's buffer-to-LDS loads of one sub-box (x, then the
+// coefficient) into `dst`.  geo[i] of a lane: row | bit << 8 | byte << 16
+// (bit: position of its rx in the row's staged mask, 31 for padding slots;
+// byte: rx * sizeof(T) + 4 * dword half).  A lane whose bit is clear (outside
+// the macro, a Dirichlet DoF of x, padding) gets an out-of-range offset,
+// which loads 0.
+template <typename T, int KIND, int S>
+__device__ __forceinline__ void march_stage(const TileArgs<T> &a, CDesc<T> *D, int4 tl, const int *geo,
+                                            LPtr<uint64_t> trow, __attribute__((address_space(3))) T *dst, int w) {
+  using C = MarchCfg<T, KIND, S>;
+  const int64_t base = D->off + static_cast<int64_t>(tl.y) * D->L;
+  const int nbytes = D->L * static_cast<int>(sizeof(T));
+  const __amdgpu_buffer_rsrc_t rx_ =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(a.x + base), 0, nbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rk_ =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(C::HASK ? a.k + base : a.x + base), 0, nbytes, 0x00020000);
+#pragma unroll
+  for (int i = 0; i < C::IPW; ++i) {
+    const int j = w + C::WPG * i;
+    if (j < C::NINS) {
+      const int gv = geo[i];
+      const int2 e = row_rec(trow, gv & 127);
+      const uint32_t bit = (static_cast<uint32_t>(e.y) >> ((gv >> 8) & 31)) & 1u;
+      const uint32_t voff = bit ? static_cast<uint32_t>(e.x) * static_cast<uint32_t>(sizeof(T)) + (gv >> 16) : 0xffffffffu;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(j < C::IPA ? rx_ : rk_,
+                                               (__attribute__((address_space(3))) void *)(dst + (j * 64) / C::DW),
+                                               4, voff, 0, 0, 0);
+    }
+  }
+}
+
+// y[addr + OFF] += v in LDS (FP64, no return), written as an instruction
+// the compiler does not track: after a buffer-to-LDS load it would otherwise
+// wait for that load before every LDS atomic, although the atomics never
+// touch the buffer being loaded.  Its completion is waited for explicitly
+// (lgkmcnt) before the barrier that ends the element work.
+template <int OFF>
+__device__ __forceinline__ void lds_add_f64(uint32_t addr, double v) {
+  asm volatile("ds_add_f64 %0, %1 offset:%2" ::"v"(addr), "v"(v), "i"(OFF) : "memory");
+}
+
+// the micro-tets of type t in the current sub-box (lane = cube); sy = LDS byte
+// address of the accumulator
+template <typename T, int KIND, int S, int t>
+__device__ __forceinline__ void march_type(CDesc<T> *D, int m, int bsum, LPtr<T> sx, LPtr<T> sk, uint32_t sy,
+                                           int lane) {
+  using C = MarchCfg<T, KIND, S>;
+  const int cx = lane % C::TX, cy = (lane / C::TX) % C::TY, cz = lane / (C::TX * C::TY);
+  if (bsum + cx + cy + cz > D->n - kLim[t]) return;
+  const int cb = cx + C::RXP * (2 * cy + C::RY * 2 * cz);
+  const TypeGeo<T> *g = D->geo + 6 * m + t;
+  T u[10], kv[10], y[10];
+#pragma unroll
+  for (int v = 0; v < 10; ++v) {
+    const int li = cb + node_off(t, v, C::RY, C::OO, C::RXP);
+    u[v] = sx[li];
+    kv[v] = C::HASK ? sk[li] : T(1);
+  }
+  p2_elem<T, C::HASK>(u, kv, cptr(g->Gp), cptr(g->Gs), y);
+  const uint32_t ab = sy + 8u * static_cast<uint32_t>(cb);
+  lds_add_f64<8 * node_off(t, 0, C::RY, C::OO, C::RXP)>(ab, double(y[0]));
+  lds_add_f64<8 * node_off(t, 1, C::RY, C::OO, C::RXP)>(ab, double(y[1]));
+  lds_add_f64<8 * node_off(t, 2, C::RY, C::OO, C::RXP)>(ab, double(y[2]));
+  lds_add_f64<8 * node_off(t, 3, C::RY, C::OO, C::RXP)>(ab, double(y[3]));
+  lds_add_f64<8 * node_off(t, 4, C::RY, C::OO, C::RXP)>(ab, double(y[4]));
+  lds_add_f64<8 * node_off(t, 5, C::RY, C::OO, C::RXP)>(ab, double(y[5]));
+  lds_add_f64<8 * node_off(t, 6, C::RY, C::OO, C::RXP)>(ab, double(y[6]));
+  lds_add_f64<8 * node_off(t, 7, C::RY, C::OO, C::RXP)>(ab, double(y[7]));
+  lds_add_f64<8 * node_off(t, 8, C::RY, C::OO, C::RXP)>(ab, double(y[8]));
+  lds_add_f64<8 * node_off(t, 9, C::RY, C::OO, C::RXP)>(ab, double(y[9]));
+}
+
+template <typename T, int KIND, int S>
+__global__ __launch_bounds__(192) void k_march(TileArgs<T> a) {
+  using C = MarchCfg<T, KIND, S>;
+  constexpr int RX = C::RX, RY = C::RY, RXP = C::RXP, OO = C::OO, ROWS = C::ROWS, RP = C::RP, PLANE = C::PLANE;
+  __shared__ T sbuf[2][C::NA * C::RPA];
+  __shared__ double sy[RP];
+  __shared__ int2 trow[2][ROWS];
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+
+  // this workgroup's segments: XCD x (workgroups are dispatched round-robin
+  // over the 8 XCDs) owns a contiguous run of the spatially ordered segment
+  // list, and its workgroups take that run's segments in turn
+  const int G = gridDim.x, x8 = blockIdx.x % 8, jw = blockIdx.x / 8;
+  const int gx = G / 8 + (x8 < G % 8 ? 1 : 0);
+  const int q = a.ntiles / 8, rem = a.ntiles % 8;
+  const int s_begin = x8 * q + min(x8, rem), s_end = s_begin + q + (x8 < rem ? 1 : 0);
+
+  // active flag of segment s's instance, read as a scalar (the aligned word holding its byte)
+  auto active = [&](int s) {
+    if (a.active == nullptr) return true;
+    const uintptr_t p = reinterpret_cast<uintptr_t>(a.active + tile_rec(a.tiles, s).x);
+    const uint32_t wv = *cptr(reinterpret_cast<const uint32_t *>(p & ~uintptr_t(3)));
+    return ((wv >> (8 * (p & 3))) & 255u) != 0u;
+  };
+  auto first_from = [&](int s) {
+    while (s < s_end && !active(s)) s += gx;
+    return s;
+  };
+  // the sub-box after `it`: the next one of its segment if it exists, else
+  // the first of this workgroup's next active segment (seg >= s_end: none)
+  auto advance = [&](MarchItem it) {
+    const int4 tl = tile_rec(a.tiles, it.seg);
+    CDesc<T> *D = (CDesc<T> *)(a.inst + tl.x);
+    const int bs = (tl.z & 1023) + ((tl.z >> 10) & 1023) + ((tl.z >> 20) & 1023);
+    if (it.sub + 1 < S && bs + C::TZS * (it.sub + 1) <= D->n - 1) return MarchItem{it.seg, it.sub + 1};
+    return MarchItem{first_from(it.seg + gx), 0};
+  };
+
+  // per-lane geometry of this wavefront's loads (see march_stage)
+  int geo[C::IPW];
+#pragma unroll
+  for (int i = 0; i < C::IPW; ++i) {
+    const int j = w + C::WPG * i;
+    const int arr = j / C::IPA;
+    const int d = (j % C::IPA) * 64 + lane;  // dword within the array
+    const int slot = d / C::DW, half = d % C::DW;
+    const int row = slot / RXP, xs = slot - row * RXP;
+    const int rx = xs < OO ? 2 * xs : (xs < OO + C::TX ? 2 * (xs - OO) + 1 : -1);
+    const bool ok = j < C::NINS && row < ROWS && rx >= 0;
+    geo[i] = ok ? (row | ((rx + 9 * arr) << 8) | ((rx * static_cast<int>(sizeof(T)) + 4 * half) << 16)) : (31 << 8);
+  }
+
+  MarchItem cur{first_from(s_begin + jw), 0};
+  if (cur.seg >= s_end) return;
+  MarchItem nxt = advance(cur);
+  int cb = 0;
+  // prologue: tables and loads of the first sub-box, tables of the second, clear the accumulator
+  if (tid < ROWS) {
+    const int4 tl = tile_rec(a.tiles, cur.seg);
+    march_row_table<T, KIND, S>((CDesc<T> *)(a.inst + tl.x), tl, cur.sub, tid, trow[0]);
+  }
+  lds_barrier();
+  {
+    const int4 tl = tile_rec(a.tiles, cur.seg);
+    march_stage<T, KIND, S>(a, (CDesc<T> *)(a.inst + tl.x), tl, geo, (LPtr<uint64_t>)trow[0],
+                            (__attribute__((address_space(3))) T *)sbuf[0], w);
+  }
+  if (nxt.seg < s_end && tid < ROWS) {
+    const int4 tl = tile_rec(a.tiles, nxt.seg);
+    march_row_table<T, KIND, S>((CDesc<T> *)(a.inst + tl.x), tl, nxt.sub, tid, trow[1]);
+  }
+  for (int s = tid; s < RP; s += C::NTH) sy[s] = 0.0;
+  wait_vmem();
+  lds_barrier();
+
+  while (true) {
+    const int nb = cb ^ 1;
+    const int4 tl = tile_rec(a.tiles, cur.seg);
+    CDesc<T> *D = (CDesc<T> *)(a.inst + tl.x);
+    const int m = tl.y;
+    const int bx0 = tl.z & 1023, by0 = (tl.z >> 10) & 1023, bz0 = (tl.z >> 20) & 1023;
+    const bool more = nxt.seg < s_end;
+    // A. loads of the next sub-box
+    if (more) {
+      const int4 tn = tile_rec(a.tiles, nxt.seg);
+      march_stage<T, KIND, S>(a, (CDesc<T> *)(a.inst + tn.x), tn, geo, (LPtr<uint64_t>)trow[nb],
+                              (__attribute__((address_space(3))) T *)sbuf[nb], w);
+    }
+    // B. micro-tets of the current sub-box
+    {
+      const LPtr<T> sx = (LPtr<T>)sbuf[cb];
+      const LPtr<T> sk = (LPtr<T>)(sbuf[cb] + (C::HASK ? C::RPA : 0));
+      const uint32_t syb = static_cast<uint32_t>(reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) double *)sy));
+      const int bsum = bx0 + by0 + bz0 + C::TZS * cur.sub;
+      if (w == 0) {
+        march_type<T, KIND, S, 0>(D, m, bsum, sx, sk, syb, lane);
+        march_type<T, KIND, S, 3>(D, m, bsum, sx, sk, syb, lane);
+      } else if (w == 1) {
+        march_type<T, KIND, S, 1>(D, m, bsum, sx, sk, syb, lane);
+        march_type<T, KIND, S, 4>(D, m, bsum, sx, sk, syb, lane);
+      } else {
+        march_type<T, KIND, S, 2>(D, m, bsum, sx, sk, syb, lane);
+        march_type<T, KIND, S, 5>(D, m, bsum, sx, sk, syb, lane);
+      }
+    }
+    // the element work's LDS atomics, the next sub-box's loads and the
+    // previous write-back's stores are complete here (s_waitcnt 0: all
+    // counters); the next iteration reads the loaded buffer after two more barriers
+    __builtin_amdgcn_s_waitcnt(0);
+    lds_barrier();
+    // C. write-back: planes 0 .. 7 of the sub-box, and plane 8 if it ends its segment
+    const bool carry = more && nxt.seg == cur.seg;
+    {
+      const int64_t base = D->off + static_cast<int64_t>(m) * D->L;
+      GPtr<T> yb = gptr(a.y + base);
+      GPtr<T> pt = gptr(D->partial) + static_cast<int64_t>(tl.w) * C::RSEG;
+      const uint32_t bnd = D->dirichlet ? *cptr(D->bnd + m) : 0u;
+      const int npts = RX * RY * (carry ? C::RZ - 1 : C::RZ);
+      const LPtr<uint64_t> tr = (LPtr<uint64_t>)trow[cb];
+      for (int r = tid; r < npts; r += C::NTH) {
+        const int row = r / RX, rx = r - row * RX;
+        const int2 e = row_rec(tr, row);
+        const uint32_t inf = static_cast<uint32_t>(e.y);
+        if (!((inf >> (9 + rx)) & 1u)) continue;
+        const T v = T(sy[lds_slot(rx, row, OO, RXP)]);
+        const bool ex = (rx & 1) || ((rx > 0 || bx0 == 0) && rx < 2 * C::TX);
+        if (((inf >> 21) & 1u) && ex) {
+          const int zp = (((inf >> 18) & 1u) && rx == static_cast<int>((inf >> 24) & 31u)) |
+                         ((bx0 == 0 && rx == 0) << 1) | (((inf >> 19) & 1u) << 2) | (((inf >> 20) & 1u) << 3);
+          __builtin_nontemporal_store(((bnd >> zp) & 1u) ? T(0) : v, &yb[e.x + rx]);
+        } else {
+          const int ry = row % RY, rz = row / RY;
+          pt[rx + RX * (ry + RY * (2 * C::TZS * cur.sub + rz))] = v;
+        }
+      }
+    }
+    lds_barrier();
+    // D. clear the accumulator (the carried face moves to plane 0) and build
+    // the tables of the sub-box after next
+    MarchItem nn{s_end, 0};
+    if (more) nn = advance(nxt);
+    for (int s = tid; s < PLANE; s += C::NTH) {
+      const double c = carry ? sy[s + (C::RZ - 1) * PLANE] : 0.0;
+      sy[s] = c;
+#pragma unroll
+      for (int p = 1; p < C::RZ; ++p) sy[s + p * PLANE] = 0.0;
+    }
+    if (nn.seg < s_end && tid < ROWS) {
+      const int4 t2 = tile_rec(a.tiles, nn.seg);
+      march_row_table<T, KIND, S>((CDesc<T> *)(a.inst + t2.x), t2, nn.sub, tid, trow[cb]);
+    }
+    if (!more) break;
+    lds_barrier();
+    cur = nxt;
+    nxt = nn;
+    cb = nb;
+  }
+}
+
+// LDS per CU that concurrently resident workgroups can actually hold on
+// gfx950 (measured: three 40 KB workgroups fit, four do not)
+constexpr int kUsableLdsPerCU = 120 * 1024;
+
+template <typename T, int KIND, int S>
+hipError_t launch_march(const TileArgs<T> &a, hipStream_t s) {
+  if (a.ntiles == 0) return hipSuccess;
+  // persistent: as many workgroups as are resident at once (at most one per
+  // segment); the occupancy query overstates how many fit in LDS, so the
+  // count is also capped by the usable LDS
+  static int resident = 0;
+  if (resident == 0) {
+    int dev = 0, ncu = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_march<T, KIND, S>, MarchCfg<T, KIND, S>::NTH, 0);
+    hipFuncAttributes fa;
+    if (e == hipSuccess) e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k_march<T, KIND, S>));
+    if (e != hipSuccess) return e;
+    const int by_lds = fa.sharedSizeBytes > 0 ? kUsableLdsPerCU / static_cast<int>(fa.sharedSizeBytes) : per;
+    resident = ncu * max(1, min(per, by_lds));
+  }
+  const int grid = a.ntiles < resident ? a.ntiles : resident;
+  hipLaunchKernelGGL((k_march<T, KIND, S>), dim3(grid), dim3(MarchCfg<T, KIND, S>::NTH), 0, s, a);
+  return hipGetLastError();
+}
+
 template <typename T, int KIND, int MAP, int TX, int TY, int TZ>
 hipError_t launch_cfg(const TileArgs<T> &a, hipStream_t s) {
   using Cfg = TileCfg<T, KIND, MAP, TX, TY, TZ>;
@@ -1358,8 +1731,26 @@ hipError_t launch_kind(const TileArgs<T> &a, int cfg, hipStream_t s) {
 
 }  // namespace
 
+template <typename T, int KIND>
+hipError_t launch_march_cfg(const TileArgs<T> &a, int cfg, hipStream_t s) {
+  switch (kTileMarch[cfg]) {
+    case 2: return launch_march<T, KIND, 2>(a, s);
+    case 4: return launch_march<T, KIND, 4>(a, s);
+    case 8: return launch_march<T, KIND, 8>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename T>
 hipError_t launch_tile_apply(const TileArgs<T> &a, int kind, int map, int cfg, hipStream_t s) {
+  if (cfg < 0 || cfg >= kNumTileCfg) return hipErrorInvalidValue;
+  if (kTileMarch[cfg] != 0) {
+    // marching tiles: the scalar P2 applies
+    if (map != 0) return hipErrorInvalidValue;
+    if (kind == P2_LAPLACE) return launch_march_cfg<T, P2_LAPLACE>(a, cfg, s);
+    if (kind == P2_DIVKGRAD) return launch_march_cfg<T, P2_DIVKGRAD>(a, cfg, s);
+    return hipErrorInvalidValue;
+  }
   switch (kind) {
     case P2_LAPLACE: return launch_kind<T, P2_LAPLACE, 0>(a, cfg, s);
     case P2_DIVKGRAD: return launch_kind<T, P2_DIVKGRAD, 0>(a, cfg, s);
@@ -1407,7 +1798,10 @@ hipError_t launch_seam_gather(const SeamInst<T> *inst, const int4 *work, int nwo
     case 0: TMF_SEAM(1, kSeamPointsPerThread, 4, 4, 4); break;
     case 1: TMF_SEAM(1, kSeamPointsPerThread, 8, 4, 2); break;
     case 2: TMF_SEAM(1, kSeamPointsPerThread, 8, 4, 4); break;
-    case 3: TMF_SEAM(1, kSeamPointsPerThread, 4, 4, 8); break;
+    case 3:
+    case 4: TMF_SEAM(1, kSeamPointsPerThread, 4, 4, 8); break;
+    case 5: TMF_SEAM(1, kSeamPointsPerThread, 4, 4, 16); break;
+    case 6: TMF_SEAM(1, kSeamPointsPerThread, 4, 4, 32); break;
     default: return hipErrorInvalidValue;
   }
 #undef TMF_SEAM

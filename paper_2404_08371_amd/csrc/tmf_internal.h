@@ -231,8 +231,14 @@ hipError_t launch_fill(T *p, int64_t n, T v, hipStream_t s);
 // rows per wavefront of the constant-coefficient P1 stencil (2.5-D blocking)
 constexpr int kStencilRows = 4;
 
-// tile shapes available to the element-centric kernels (micro-cubes per tile)
-constexpr int kNumTileCfg = 4;
-constexpr int kTileCfg[kNumTileCfg][3] = {{4, 4, 4}, {8, 4, 2}, {8, 4, 4}, {4, 4, 8}};
+// tile shapes available to the element-centric kernels (micro-cubes per
+// tile).  The first kNumClassicTileCfg are boxes staged whole by one
+// workgroup; the others are column segments of kTileMarch[cfg] sub-boxes of
+// 4 x 4 x 4 cubes walked in z by the persistent marching kernel (scalar P2
+// applies only; the other modes of those operators use a box shape).
+constexpr int kNumTileCfg = 7;
+constexpr int kNumClassicTileCfg = 4;
+constexpr int kTileCfg[kNumTileCfg][3] = {{4, 4, 4}, {8, 4, 2}, {8, 4, 4}, {4, 4, 8}, {4, 4, 8}, {4, 4, 16}, {4, 4, 32}};
+constexpr int kTileMarch[kNumTileCfg] = {0, 0, 0, 0, 2, 4, 8};
 
 }  // namespace tmf

@@ -49,8 +49,9 @@ def test_diagonal_matches_oracle(mesh, level, kind, bc, prec):
     assert ei <= (1e-12 if prec == T.F64 else 1e-5), (e2, ei)
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("cfg", list(range(7)))
 def test_diagonal_every_tile_shape(cfg):
+    """Every tile shape the apply may use; with a marching shape the diagonal runs on a box shape."""
     print("diag tile", cfg, flush=True)
     m, op = lib_op("cube", 4, O.P2_DIVKGRAD, O.BC_DIRICHLET_ZERO, T.F64)
     T.check(T.lib().tmf_op_set_tile(op.handle, cfg))

@@ -77,7 +77,13 @@ def test_fp32_parity(mesh, level, kind):
     assert ei <= 1e-5, (e2, ei)
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+# tile shapes of the scalar P2 kinds: 4 boxes, then 3 marching column segments
+# (2, 4 and 8 sub-boxes of 4 x 4 x 4 cubes)
+ALL_TILES = list(range(7))
+MARCH_TILES = [4, 5, 6]
+
+
+@pytest.mark.parametrize("cfg", ALL_TILES)
 @pytest.mark.parametrize("kind,prec", [(O.P2_DIVKGRAD, T.F64), (O.P2_LAPLACE, T.F64), (O.P2_DIVKGRAD, T.F32)])
 def test_every_tile_shape(cfg, kind, prec):
     """Each autotuner candidate computes the same operator (level 4: 16 cubes per edge, ragged boxes)."""
@@ -122,7 +128,32 @@ def test_local_apply_then_interface_sum_is_the_apply(mesh, level, kind, bc):
         assert e2 <= 1e-12 and ei <= 1e-12, (e2, ei)
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("cfg", MARCH_TILES)
+@pytest.mark.parametrize("mesh,level", [("ref", 0), ("ref", 1), ("ref", 3), ("ref", 5), ("cube", 2), ("cube", 5),
+                                        ("flatshell", 3)])
+@pytest.mark.parametrize("bc", [O.BC_DIRICHLET_ZERO, O.BC_NONE])
+@pytest.mark.parametrize("kind,prec", [(O.P2_DIVKGRAD, T.F64), (O.P2_LAPLACE, T.F64), (O.P2_DIVKGRAD, T.F32)])
+def test_marching_tiles(cfg, mesh, level, bc, kind, prec):
+    """The marching kernel on single macros and multi-macro meshes at levels where a segment holds
+    one sub-box (levels 0-2), where segments are cut short by the macro's diagonal face, and where
+    several segments stack in z (level 5: 32 cubes per edge), with both boundary conditions.  Outputs
+    start as NaN, so a slot that no kernel writes shows."""
+    print("march case", cfg, mesh, level, bc, kind, prec, flush=True)
+    m, op = lib_problem(mesh, level, kind, bc, prec)
+    T.check(T.lib().tmf_op_set_tile(op.handle, cfg))
+    info = m.dof_info(2, owner=False, boundary=False)
+    x, k = inputs(kind, info["keys"], info["xyz"], 8)
+    dt = torch.float64 if prec == T.F64 else torch.float32
+    xt = torch.tensor(x, dtype=dt, device="cuda")
+    y = op.apply(xt, torch.tensor(k, dtype=dt, device="cuda") if k is not None else None,
+                 out=torch.full_like(xt, float("nan")))
+    assert not torch.isnan(y).any()
+    pr = oracle_problem(mesh, level, kind, bc)
+    e2, ei = rel_err(y.double().cpu().numpy(), pr.apply(*inputs(kind, pr.keys, pr.xyz, 8)))
+    assert ei <= (1e-12 if prec == T.F64 else 1e-5), (e2, ei)
+
+
+@pytest.mark.parametrize("cfg", ALL_TILES)
 def test_repeated_applies_agree(cfg):
     """Every entry of y is written by exactly one thread (outputs start as NaN);
     repeated applies agree to rounding of the in-box LDS accumulation."""

@@ -16,7 +16,7 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("cfg", list(range(7)))
 @pytest.mark.parametrize("bc", [O.BC_DIRICHLET_ZERO, O.BC_NONE])
 @pytest.mark.parametrize("prec", [T.F64, T.F32])
 def test_stored_apply_matches_oracle(cfg, bc, prec):
@@ -31,7 +31,7 @@ def test_stored_apply_matches_oracle(cfg, bc, prec):
     x = torch.tensor(W.uniform_from_keys(4, info["keys"]), dtype=dt, device="cuda")
     op.store_matrices(k)
     # a later change of tile shape does not affect the stored layout
-    T.check(T.lib().tmf_op_set_tile(op.handle, (cfg + 1) % 4))
+    T.check(T.lib().tmf_op_set_tile(op.handle, (cfg + 1) % 7))
     y = op.apply_stored(x, out=torch.full_like(x, float("nan"))).double().cpu().numpy()
     assert not np.isnan(y).any()
     pr = oracle_problem("cube", 4, O.P2_DIVKGRAD, bc)
