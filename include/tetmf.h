@@ -189,6 +189,22 @@ tmf_status tmf_op_info(const tmf_op *op, int64_t *n_local, int64_t *n_unique, in
  * x, y: ncomp * n_local values; y must not alias x or coeff. */
 tmf_status tmf_apply(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream);
 
+/* tmf_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * operation and arguments, with the seam partial sums of the P2 and epsilon
+ * kinds (the apply's only device memory beyond x, coeff and y) in a static
+ * device array of 64 MiB that every GPU the library is loaded on holds until
+ * the process ends, instead of the operator's own buffer.  Allocates nothing
+ * and never synchronises.  All calls on one GPU share that array: calls whose
+ * executions overlap on a GPU (several streams, or a graph replayed
+ * concurrently) race and give wrong results; calls ordered on one stream are
+ * safe (no state carries over between calls).  P1 kinds use no scratch and
+ * behave as tmf_apply.  Errors as tmf_apply, and TMF_EINVAL when the
+ * operator's partial sums at its current tile shape exceed 64 MiB (the
+ * message gives both sizes; e.g. the P2 FP64 cube of 6 macros at level 6
+ * needs about 29 MB, at level 7 about 230 MB). */
+tmf_status tmf_apply_noalloc(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream);
+
 /* The macro-local part of the apply: y = sum over macros M of the sum over
  * micro-tets T of M of P_T A_T R_T x, i.e. tmf_apply without the final
  * interface sum.  On a DoF shared by several macros each copy holds only its

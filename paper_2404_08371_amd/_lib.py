@@ -32,6 +32,7 @@ SIGNATURES = [
     ("tmf_apply", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     ("tmf_apply_adjoint", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     ("tmf_apply_timed", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    ("tmf_apply_noalloc", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     ("tmf_apply_local", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     ("tmf_interface_sum", c_int, [c_vp, c_vp, c_vp]),
     ("tmf_diagonal", c_int, [c_vp, c_vp, c_vp, c_vp]),

@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -555,6 +556,7 @@ tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const
       if (st == TMF_OK) st = op->seam[cfg].upload(pts.data(), pts.size());
       const size_t R = static_cast<size_t>(2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1);
       const size_t per_tile = R * op->ncomp * (prec == TMF_F64 ? 8 : 4);
+      op->partial_bytes[cfg] = tl.size() * per_tile;
       partial_bytes = std::max(partial_bytes, tl.size() * per_tile);
       // the gather addresses one macro's partial sums by 32-bit byte offsets
       if (st == TMF_OK && (tl.size() / static_cast<size_t>(mesh->nt)) * per_tile > 0xffffffffull)
@@ -682,7 +684,8 @@ GroupArgs group_args(const tmf_op *op) {
 template <typename T>
 hipError_t tile_path(tmf_op *op, int kind, const void *coeff, const void *x, T *yy, hipStream_t s, hipEvent_t ev0,
                      hipEvent_t ev1, bool interface, const void *x2 = nullptr, int seam_flags = 0,
-                     int ncomp_out = 0, void *mat = nullptr, int cfg = -1, bool gather = true) {
+                     int ncomp_out = 0, void *mat = nullptr, int cfg = -1, bool gather = true,
+                     T *partial = nullptr) {
   hipError_t e;
   const int c = cfg >= 0 ? cfg : mode_cfg(op->tile_cfg, op->classic_cfg, kind);
   TileArgs<T> a;
@@ -697,6 +700,7 @@ hipError_t tile_path(tmf_op *op, int kind, const void *coeff, const void *x, T *
   a.x = static_cast<const T *>(x);
   a.x2 = static_cast<const T *>(x2);
   a.y = yy;
+  a.partial = partial;
   if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
   e = launch_tile_apply<T>(a, kind, op->mesh->map, c, s);
   if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
@@ -705,13 +709,15 @@ hipError_t tile_path(tmf_op *op, int kind, const void *coeff, const void *x, T *
                               op->seamwork[c].p + (interface ? 0 : op->ngroupwork[c]),
                               interface ? op->nseamwork[c] : op->nseamonly[c], yy, nullptr,
                               (interface ? 0 : kSeamLocal) | seam_flags,
-                              ncomp_out ? ncomp_out : op->ncomp, seam_ppt(op), c, seam_rows_lds(op->seamrows[c]), s);
+                              ncomp_out ? ncomp_out : op->ncomp, seam_ppt(op), c, seam_rows_lds(op->seamrows[c]), s,
+                              partial);
   return e;
 }
 
 template <typename T>
 hipError_t apply_t(tmf_op *op, const void *coeff, const void *x, void *y, hipStream_t s,
-                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool interface = true) {
+                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool interface = true,
+                   T *partial = nullptr) {
   hipError_t e;
   T *yy = static_cast<T *>(y);
   if (op->space == 1) {
@@ -726,7 +732,7 @@ hipError_t apply_t(tmf_op *op, const void *coeff, const void *x, void *y, hipStr
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
   } else {
     const int mode = op->kind == TMF_P2_DIVKGRAD && op->nq > 0 ? P2_DIVKGRAD_Q : op->kind;
-    return tile_path<T>(op, mode, coeff, x, yy, s, ev0, ev1, interface);
+    return tile_path<T>(op, mode, coeff, x, yy, s, ev0, ev1, interface, nullptr, 0, 0, nullptr, -1, true, partial);
   }
   if (e != hipSuccess || !interface) return e;
   return launch_interface_sum<T>(group_args(op), yy, s);
@@ -784,6 +790,64 @@ tmf_status tmf_apply_timed(tmf_op *op, const void *coeff, const void *x, void *y
 
 tmf_status tmf_apply(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream) {
   return tmf_apply_timed(op, coeff, x, y, stream, nullptr, nullptr);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free apply.  The seam partial sums of one apply (the only device
+// memory an apply uses beyond its inputs and outputs) go to a static device
+// array of kScratchBytes, which the runtime places on every GPU the library
+// is loaded on, instead of to the operator's own buffer.  Its device address
+// is looked up once per device, on the first call with that device current.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {nullptr};
+
+tmf_status scratch_address(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(TMF_EUNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[dev] == nullptr) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the static scratch");
+    if (p == nullptr) return fail(TMF_EDEVICE, "the static scratch has no device address");
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return TMF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+tmf_status tmf_apply_noalloc(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream) {
+  tmf_status st = check_apply(op, coeff, x, y);
+  if (st != TMF_OK) return st;
+  void *ptr = nullptr;
+  if (op->space == 2) {
+    // the tile shape the apply runs with, and the partial sums it writes
+    const int mode = op->kind == TMF_P2_DIVKGRAD && op->nq > 0 ? P2_DIVKGRAD_Q : op->kind;
+    const int c = mode_cfg(op->tile_cfg, op->classic_cfg, mode);
+    if (op->partial_bytes[c] > kScratchBytes)
+      return fail(TMF_EINVAL, "this apply needs %zu bytes of partial sums; the static scratch holds %zu",
+                  op->partial_bytes[c], kScratchBytes);
+    st = scratch_address(&ptr);
+    if (st != TMF_OK) return st;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = op->prec == TMF_F64
+                     ? apply_t<double>(op, coeff, x, y, s, nullptr, nullptr, true, static_cast<double *>(ptr))
+                     : apply_t<float>(op, coeff, x, y, s, nullptr, nullptr, true, static_cast<float *>(ptr));
+  if (e != hipSuccess) return hip_fail(e, "apply launch");
+  return TMF_OK;
 }
 
 tmf_status tmf_apply_local(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream) {

@@ -91,6 +91,7 @@ struct tmf_op {
   DevBuf<int> seam[kNumTileCfg], rowstart[kNumTileCfg];
   int nseam[kNumTileCfg] = {0}, nby[kNumTileCfg] = {0}, tpm[kNumTileCfg] = {0};
   DevBuf<uint8_t> partial;
+  size_t partial_bytes[kNumTileCfg] = {0};  // partial sums of one apply, per tile shape
   DevBuf<uint8_t> seaminst[kNumTileCfg];  // one SeamInst of the op's precision
   DevBuf<int4> seamwork[kNumTileCfg];     // interface-group entries, then seam entries
   int nseamwork[kNumTileCfg] = {0}, nseamonly[kNumTileCfg] = {0}, ngroupwork[kNumTileCfg] = {0};

@@ -1124,7 +1124,7 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
 
   // 3. write back: points of this box alone go to y (Dirichlet DoFs as 0),
   // points of shared box faces to this tile's partials [component][box point]
-  GPtr<T> pt = gptr(D->partial) + static_cast<int64_t>(tl.w) * NC * R;
+  GPtr<T> pt = gptr(a.partial ? a.partial : D->partial) + static_cast<int64_t>(tl.w) * NC * R;
   for (int r = tid; r < R; r += NTH) {
     const int row = r / RX, rx = r - row * RX;
     const int info = sri[row], lim = info >> 8, qi = 2 * bx0 + rx;
@@ -1164,9 +1164,9 @@ __device__ __forceinline__ bool is_seam(int qx, int qy, int qz) {
 // at the largest level, so a candidate is addressed by the block's 64-bit base
 // (uniform over a seam work entry) and a 32-bit byte offset.
 template <typename T, int NC, int TX, int TY, int TZ>
-__device__ __forceinline__ GPtr<const char> partial_block(const SeamInst<T> &a, int m) {
+__device__ __forceinline__ GPtr<const char> partial_block(const SeamInst<T> &a, const T *ovr, int m) {
   constexpr int R = (2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1);
-  return (GPtr<const char>)gptr(a.partial + static_cast<int64_t>(m) * a.tpm * NC * R);
+  return (GPtr<const char>)gptr((ovr ? ovr : a.partial) + static_cast<int64_t>(m) * a.tpm * NC * R);
 }
 
 template <typename T, int NC, int TX, int TY, int TZ, typename RS>
@@ -1225,7 +1225,8 @@ __device__ __forceinline__ void seam_sum(const SeamInst<T> &a, RS rs, GPtr<const
 template <typename T, int NC, int PPT, int TX, int TY, int TZ>
 __global__ __launch_bounds__(256, 5) void k_seam(const SeamInst<T> *__restrict__ insts,
                                                  const int4 *__restrict__ work, T *__restrict__ y,
-                                                 const uint8_t *__restrict__ active, int flags, int rows_lds) {
+                                                 const uint8_t *__restrict__ active, int flags, int rows_lds,
+                                                 const T *__restrict__ partial) {
   const bool local = flags & kSeamLocal;
   extern __shared__ int srs[];
   __shared__ T sv[NC][256];
@@ -1275,7 +1276,7 @@ __global__ __launch_bounds__(256, 5) void k_seam(const SeamInst<T> *__restrict__
       // load of one point above the store of another: y and the partials may alias)
       const uint32_t bm = a.dirichlet && !(flags & kSeamKeepBoundary) ? *cptr(a.bnd + m) : 0u;
       const uint32_t sh = local ? 0u : *cptr(a.shared + m);
-      const GPtr<const char> pmw = partial_block<T, NC, TX, TY, TZ>(a, w.y);
+      const GPtr<const char> pmw = partial_block<T, NC, TX, TY, TZ>(a, partial, w.y);
       T acc[PPT][NC];
       int64_t sl[PPT];
       bool wr[PPT], dz[PPT];
@@ -1307,7 +1308,7 @@ __global__ __launch_bounds__(256, 5) void k_seam(const SeamInst<T> *__restrict__
     if (mine) {
       T v[NC];
       if (is_seam<TX, TY, TZ>(qx, qy, qz)) {
-        seam_sum<T, NC, TX, TY, TZ>(a, rs, partial_block<T, NC, TX, TY, TZ>(a, m), qx, qy, qz, v);
+        seam_sum<T, NC, TX, TY, TZ>(a, rs, partial_block<T, NC, TX, TY, TZ>(a, partial, m), qx, qy, qz, v);
       } else {
 #pragma unroll
         for (int c = 0; c < NC; ++c) v[c] = yi[slot + c * a.n_local];
@@ -1638,7 +1639,7 @@ __global__ __launch_bounds__(192) void k_march(TileArgs<T> a) {
     {
       const int64_t base = D->off + static_cast<int64_t>(m) * D->L;
       GPtr<T> yb = gptr(a.y + base);
-      GPtr<T> pt = gptr(D->partial) + static_cast<int64_t>(tl.w) * C::RSEG;
+      GPtr<T> pt = gptr(a.partial ? a.partial : D->partial) + static_cast<int64_t>(tl.w) * C::RSEG;
       const uint32_t bnd = D->dirichlet ? *cptr(D->bnd + m) : 0u;
       const int npts = RX * RY * (carry ? C::RZ - 1 : C::RZ);
       const LPtr<uint64_t> tr = (LPtr<uint64_t>)trow[cb];
@@ -1779,13 +1780,14 @@ template hipError_t launch_tile_apply<float>(const TileArgs<float> &, int, int, 
 
 template <typename T>
 hipError_t launch_seam_gather(const SeamInst<T> *inst, const int4 *work, int nwork, T *y, const uint8_t *active,
-                              int flags, int ncomp, int ppt, int cfg, int rows_lds, hipStream_t s) {
+                              int flags, int ncomp, int ppt, int cfg, int rows_lds, hipStream_t s,
+                              const T *partial) {
   if (nwork == 0) return hipSuccess;
   const dim3 grid(nwork);
   const size_t sh = static_cast<size_t>(rows_lds) * sizeof(int);
 #define TMF_SEAM(NC_, PPT_, TX_, TY_, TZ_)                                                                   \
   hipLaunchKernelGGL((k_seam<T, NC_, PPT_, TX_, TY_, TZ_>), grid, dim3(256), sh, s, inst, work, y, active, flags, \
-                     rows_lds)
+                     rows_lds, partial)
   if (ncomp == 3 || ppt == 1) {
     // vector fields and the scalar gradient of a vector operator: cfg 0, one point per thread
     if (cfg != 0 || ppt != 1) return hipErrorInvalidValue;
@@ -1809,8 +1811,8 @@ hipError_t launch_seam_gather(const SeamInst<T> *inst, const int4 *work, int nwo
 }
 
 template hipError_t launch_seam_gather<double>(const SeamInst<double> *, const int4 *, int, double *,
-                                               const uint8_t *, int, int, int, int, int, hipStream_t);
+                                               const uint8_t *, int, int, int, int, int, hipStream_t, const double *);
 template hipError_t launch_seam_gather<float>(const SeamInst<float> *, const int4 *, int, float *, const uint8_t *,
-                                              int, int, int, int, int, hipStream_t);
+                                              int, int, int, int, int, hipStream_t, const float *);
 
 }  // namespace tmf

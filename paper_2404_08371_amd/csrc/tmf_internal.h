@@ -162,6 +162,7 @@ struct TileArgs {
   const T *x2 = nullptr;  // second staged input (gy of the coefficient-gradient mode)
   T *mat = nullptr;       // stored local matrices [tile][type][entry][cube]
   T *y;
+  T *partial = nullptr;   // if set, the tile partial sums go here instead of the instance's own buffer
 };
 
 struct GroupArgs {
@@ -220,9 +221,11 @@ hipError_t launch_tile_apply(const TileArgs<T> &a, int kind, int map, int tile_c
 constexpr int kSeamLocal = 1, kSeamKeepBoundary = 2;
 template <typename T>
 // ncomp: components of y; ppt: seam points per thread, as the work list was
-// chunked (256 ppt points per seam entry)
+// chunked (256 ppt points per seam entry); partial: if set, the tile partial
+// sums are read from it instead of each instance's own buffer (one instance)
 hipError_t launch_seam_gather(const SeamInst<T> *inst, const int4 *work, int nwork, T *y, const uint8_t *active,
-                              int flags, int ncomp, int ppt, int tile_cfg, int rows_lds, hipStream_t s);
+                              int flags, int ncomp, int ppt, int tile_cfg, int rows_lds, hipStream_t s,
+                              const T *partial = nullptr);
 template <typename T>
 hipError_t launch_interface_sum(const GroupArgs &g, T *y, hipStream_t s);
 template <typename T>
