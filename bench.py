@@ -296,6 +296,23 @@ def batched_solve(torch, T, W, hip, steps):
                     "max_relres_fp64" + tag: float(relres.max()), "rel_err_vs_exact" + tag: err,
                     "converged" + tag: stats["converged"]})
         del solver
+    # the plain FP64 form on the same GPU: Jacobi-preconditioned CG with the FP64 apply and FP64
+    # vectors (the same solver with the FP64 batch as its inner batch, inner tolerance below the
+    # outer one, so the first outer step solves and the second confirms)
+    solver = T.IRSolver(b64, b64, tol=1e-10, inner_rtol=1e-11, precond=T.PRECOND_JACOBI)
+    X = torch.zeros_like(B)
+    solver.solve(B, X, K, K)  # warm-up (graph capture)
+    X.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats, relres = solver.solve(B, X, K, K)
+    tsol = time.perf_counter() - t0
+    err = float(((X - Xs).norm() / Xs.norm()).item())
+    res.update({"solve_s_fp64_cg": round(tsol, 4), "outer_fp64_cg": stats["outer"],
+                "inner_iterations_fp64_cg": stats["inner_total"], "max_relres_fp64_cg": float(relres.max()),
+                "rel_err_vs_exact_fp64_cg": err, "converged_fp64_cg": stats["converged"],
+                "refined_speedup_vs_fp64_cg": round(tsol / res["solve_s"], 3)})
+    del solver
     return res
 
 

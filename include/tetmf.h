@@ -224,9 +224,14 @@ tmf_status tmf_interface_sum(tmf_op *op, void *v, tmf_stream stream);
  * smoothers).  d_i = sum over the micro-tets T containing DoF i of
  * (A_T)_ii, summed over the copies of a shared DoF (every copy receives the
  * total); with TMF_BC_DIRICHLET_ZERO the rows of boundary DoFs are 0, as in
- * D A D.  coeff as for tmf_apply; d: n_local values of the op's precision
- * (device), must not alias coeff.  Asynchronous on `stream`.  Kinds other
- * than TMF_P2_LAPLACE and TMF_P2_DIVKGRAD return TMF_EUNSUPPORTED. */
+ * D A D.  coeff as for tmf_apply; d: ncomp * n_local values of the op's
+ * precision (device; for TMF_P2V_EPSILON the diagonal of each component block,
+ * component-major like x), must not alias coeff.  Asynchronous on `stream`.
+ * Provided for the P1 kinds, the exactly integrated scalar P2 kinds and the
+ * epsilon operator (affine or blended; on the blended shell each micro-tet's
+ * 30 diagonal entries are formed by applying its element to unit vectors);
+ * TMF_N1_CURLCURL and the quadrature variant of TMF_P2_DIVKGRAD return
+ * TMF_EUNSUPPORTED. */
 tmf_status tmf_diagonal(tmf_op *op, const void *coeff, void *d, tmf_stream stream);
 
 /* The precomputed-matrix alternative to the matrix-free apply (the paper's
@@ -269,10 +274,16 @@ tmf_status tmf_apply_adjoint(tmf_op *op, const void *coeff, const void *x, const
 tmf_status tmf_apply_timed(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream,
                            void *ev_before, void *ev_after);
 
-/* Tile shapes of the element-centric (P2, epsilon) kernels.  Each shape is a
- * box of micro-cubes staged in LDS by one workgroup; tmf_op_num_tiles gives
- * the number of shapes valid for the op's kind (1 for P1 kinds, whose
- * kernels are vertex-centric), tmf_op_tile_shape the cubes per box edge. */
+/* Tile shapes of the element-centric (P2, epsilon, N1) kernels.  Shapes 0-3
+ * are boxes of micro-cubes staged in LDS by one workgroup (4x4x4, 8x4x2,
+ * 8x4x4, 4x4x8); shapes 4-6 are column segments of 2, 4 and 8 sub-boxes of
+ * 4x4x4 cubes (4x4x8, 4x4x16, 4x4x32) walked in z by a persistent workgroup,
+ * for the exactly integrated scalar P2 applies (their other modes -- diagonal,
+ * adjoint's coefficient gradient, stored matrices -- then run on the best box
+ * shape).  tmf_op_num_tiles gives the number of shapes valid for the op's
+ * kind (1 for P1 kinds, whose kernels are vertex-centric; 2 for epsilon: the
+ * 64-cube boxes; 4 for N1 and the quadrature variant; 7 for the exact scalar
+ * P2 kinds), tmf_op_tile_shape the cubes per tile edge. */
 tmf_status tmf_op_num_tiles(const tmf_op *op, int *count);
 tmf_status tmf_op_tile_shape(const tmf_op *op, int cfg, int *tx, int *ty, int *tz);
 tmf_status tmf_op_set_tile(tmf_op *op, int cfg);
@@ -286,9 +297,22 @@ tmf_status tmf_op_get_tile(const tmf_op *op, int *cfg);
 tmf_status tmf_op_autotune(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream,
                            int reps, int *best_cfg, float *best_ms);
 
+/* tmf_op_autotune with a result cache: a JSON file (host path) mapping a key
+ * (operator kind, precision, boundary condition, rule size, map, level, macro
+ * count, device architecture and compute units) to the chosen tile shape, the
+ * box shape used by the modes marching shapes do not provide, and the time.
+ * If the key is present, its shapes are set on the op without timing
+ * (best_ms = the cached time); otherwise the shapes are timed as by
+ * tmf_op_autotune and the result is added to the file (created if missing,
+ * rewritten through a temporary file).  cache_json_path NULL: plain
+ * autotune.  TMF_EINVAL if the file exists but is not such a cache or cannot
+ * be written. */
+tmf_status tmf_op_tune(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream, int reps,
+                       const char *cache_json_path, int *best_cfg, float *best_ms);
+
 /* ---------------------------------------------------------------- batches
- * A batch applies `count` operator instances in one persistent launch of the
- * element kernel (instances may have different meshes, levels and
+ * A batch applies `count` operator instances in one launch of the element
+ * kernel (instances may have different meshes, levels and
  * coefficients).  All operators must be P2 kinds (TMF_P2_LAPLACE,
  * TMF_P2_DIVKGRAD or TMF_P2V_EPSILON) of one kind and one precision on affine
  * meshes; they must outlive the batch.  Vectors are concatenated: instance i
@@ -314,17 +338,24 @@ tmf_status tmf_batch_set_tile(tmf_batch *batch, int cfg);
 /* Autotuner over the tile shapes for the whole batch (as tmf_op_autotune). */
 tmf_status tmf_batch_autotune(tmf_batch *batch, const void *coeff, const void *x, void *y, tmf_stream stream,
                               int reps, int *best_cfg, float *best_ms);
+/* Batch autotuner with the result cache of tmf_op_tune (key: kind,
+ * precision, each instance's level and macro count in order, device). */
+tmf_status tmf_batch_tune(tmf_batch *batch, const void *coeff, const void *x, void *y, tmf_stream stream, int reps,
+                          const char *cache_json_path, int *best_cfg, float *best_ms);
 
 /* ------------------------------------------------ mixed-precision solver
  * Iterative refinement for A_i x_i = b_i over a batch: outer iterations in
  * FP64 (r = b - A x with the FP64 batch, norms, x += |r| d), inner
- * conjugate-gradient corrections A d = r / |r| with the FP32 batch and
- * FP64-accumulated dot products, started from d = 0 and stopped per instance
- * when r.r (r.z with the Jacobi preconditioner) has fallen to inner_rtol^2
- * times its start value, or after inner_maxit iterations.  Blocks of
- * graph_iters inner iterations are captured once into a HIP graph and
- * replayed (use_graph = 0 runs the same kernels eagerly).  An instance stops
- * when |b - A x| <= tol |b| (2-norms over distinct DoFs). */
+ * conjugate-gradient corrections A d = r / |r| with the inner batch (FP32:
+ * the mixed-precision solve; or FP64: plain FP64 CG, the comparison form)
+ * and FP64-accumulated dot products, started from d = 0 and stopped per
+ * instance when r.r (r.z with the Jacobi preconditioner) has fallen to
+ * inner_rtol^2 times its start value, or after inner_maxit iterations.
+ * Blocks of graph_iters inner iterations are captured once into a HIP graph
+ * and replayed (use_graph = 0 runs the same kernels eagerly).  An instance
+ * stops when |b - A x| <= tol |b| (2-norms over distinct DoFs).  With an FP64
+ * inner batch and inner_rtol below tol, the first outer step is a plain
+ * (Jacobi-preconditioned) FP64 CG solve to tol and the second confirms it. */
 typedef struct tmf_ir tmf_ir;
 /* Inner preconditioner: none, or Jacobi (z = D^-1 r with D = diag(A) of the
  * FP64 operators, assembled by tmf_batch_diagonal at the start of each solve;
@@ -336,7 +367,7 @@ typedef struct {
   int max_outer;      /* outer steps */
   double inner_rtol;  /* inner relative residual, e.g. 1e-4 */
   int inner_maxit;    /* inner iterations per outer step */
-  int graph_iters;    /* inner iterations per graph launch */
+  int graph_iters;    /* inner iterations per graph launch (even, >= 2) */
   int use_graph;      /* 1: replay a captured HIP graph */
   int precond;        /* TMF_PRECOND_NONE or TMF_PRECOND_JACOBI */
 } tmf_ir_options;
@@ -348,18 +379,20 @@ typedef struct {
   double seconds;      /* wall time of the solve */
 } tmf_ir_stats;
 /* Both batches hold the same instances (same meshes and boundary conditions),
- * b64 in FP64 and b32 in FP32, scalar kinds only; opt may be NULL for the
- * defaults {1e-10, 30, 1e-4, 2000, 16, 1, TMF_PRECOND_JACOBI}.  Allocates the
- * device workspace (6 vectors of the batch length, 7 with Jacobi) and a
- * private stream.  Jacobi needs a scalar P2 kind (TMF_EUNSUPPORTED otherwise). */
+ * b64 in FP64 and the inner batch b32 in FP32 or FP64 (it may be b64 itself),
+ * scalar kinds only; opt may be NULL for the defaults {1e-10, 30, 1e-4, 2000,
+ * 16, 1, TMF_PRECOND_JACOBI}.  Allocates the device workspace (2 FP64 vectors
+ * and 4 inner vectors of the batch length, 5 with Jacobi) and a private
+ * stream.  Jacobi needs a scalar P2 kind (TMF_EUNSUPPORTED otherwise). */
 tmf_status tmf_ir_create(tmf_batch *b64, tmf_batch *b32, const tmf_ir_options *opt, tmf_ir **out);
 void tmf_ir_destroy(tmf_ir *solver);
 /* Solve in place: x (device, FP64, initial guess on entry), b (device, FP64),
- * coefficients in FP64 and FP32 (device; NULL for constant-coefficient kinds).
+ * coefficients in FP64 and in the inner batch's precision (device; NULL for
+ * constant-coefficient kinds).
  * Ordered after the work already queued on `stream`; blocks until done.
  * relres (host, count doubles, may be NULL) receives the final FP64 relative
  * residuals.  Returns TMF_ENOTCONV if max_outer steps were not enough. */
-tmf_status tmf_ir_solve(tmf_ir *solver, const double *coeff64, const float *coeff32, const double *b, double *x,
+tmf_status tmf_ir_solve(tmf_ir *solver, const double *coeff64, const void *coeff_inner, const double *b, double *x,
                         tmf_ir_stats *stats, double *relres, tmf_stream stream);
 
 #ifdef __cplusplus

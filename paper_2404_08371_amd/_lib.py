@@ -45,6 +45,8 @@ SIGNATURES = [
     ("tmf_op_get_tile", c_int, [c_vp, ctypes.POINTER(c_int)]),
     ("tmf_op_autotune", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(c_int),
                                 ctypes.POINTER(ctypes.c_float)]),
+    ("tmf_op_tune", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_int, ctypes.c_char_p, ctypes.POINTER(c_int),
+                            ctypes.POINTER(ctypes.c_float)]),
     ("tmf_batch_create", c_int, [ctypes.POINTER(c_vp), c_int, ctypes.POINTER(c_vp)]),
     ("tmf_batch_destroy", None, [c_vp]),
     ("tmf_batch_info", c_int, [c_vp, ctypes.POINTER(c_int), c_i64p]),
@@ -54,6 +56,8 @@ SIGNATURES = [
     ("tmf_batch_set_tile", c_int, [c_vp, c_int]),
     ("tmf_batch_autotune", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(c_int),
                                    ctypes.POINTER(ctypes.c_float)]),
+    ("tmf_batch_tune", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_int, ctypes.c_char_p, ctypes.POINTER(c_int),
+                               ctypes.POINTER(ctypes.c_float)]),
     ("tmf_ir_create", c_int, [c_vp, c_vp, c_vp, ctypes.POINTER(c_vp)]),
     ("tmf_ir_destroy", None, [c_vp]),
     ("tmf_ir_solve", c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(ctypes.c_double), c_vp]),

@@ -1,4 +1,4 @@
-"""Batched operators and the mixed-precision iterative-refinement CG solver."""
+"""Batched operators and the iterative-refinement CG solver (FP32 or FP64 inner iteration)."""
 import ctypes
 
 import numpy as np
@@ -23,7 +23,7 @@ class IRStats(ctypes.Structure):
 
 
 class Batch:
-    """Many operator instances applied in one persistent launch (vectors concatenated)."""
+    """Many operator instances applied in one launch of the element kernel (vectors concatenated)."""
 
     def __init__(self, ops):
         self.ops = list(ops)  # keeps the operators alive
@@ -90,13 +90,25 @@ class Batch:
                                        ctypes.byref(cfg), ctypes.byref(ms)))
         return cfg.value, ms.value
 
+    def tune(self, x, coeff=None, y=None, reps=5, cache=None):
+        """tmf_batch_tune: autotune with an optional JSON result cache; returns (cfg, ms)."""
+        if y is None:
+            y = torch.empty_like(x)
+        cfg, ms = ctypes.c_int(), ctypes.c_float()
+        check(lib().tmf_batch_tune(self._h, self._ptr(coeff, "coeff") if self.has_coeff else None,
+                                   self._ptr(x, "x"), self._ptr(y, "y"), _stream_handle(x.device), int(reps),
+                                   cache.encode() if cache else None, ctypes.byref(cfg), ctypes.byref(ms)))
+        return cfg.value, ms.value
+
     def __del__(self):
         release(getattr(self, "_h", None), "tmf_batch_destroy")
         self._h = None
 
 
 class IRSolver:
-    """FP64 iterative refinement around FP32 CG over a pair of batches (FP64, FP32)."""
+    """FP64 iterative refinement around an inner CG over a pair of batches: the FP64 batch for the
+    outer residual, and the inner batch, FP32 (mixed precision) or FP64 (plain FP64 CG, e.g. the
+    FP64 batch itself with inner_rtol below tol)."""
 
     def __init__(self, b64, b32, tol=1e-10, max_outer=30, inner_rtol=1e-4, inner_maxit=2000, graph_iters=16,
                  use_graph=True, precond=PRECOND_JACOBI):
@@ -107,7 +119,8 @@ class IRSolver:
         self._h = h
 
     def solve(self, b, x, coeff64=None, coeff32=None, raise_on_notconv=True):
-        """Solves in place into x (FP64 device tensor); returns (stats dict, relres array)."""
+        """Solves in place into x (FP64 device tensor); returns (stats dict, relres array).
+        coeff32 is the coefficient in the inner batch's precision."""
         st = IRStats()
         rel = np.zeros(self.b64.count)
         pk64 = self.b64._ptr(coeff64, "coeff64") if self.b64.has_coeff else None

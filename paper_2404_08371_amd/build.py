@@ -15,7 +15,8 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libtetmf.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["host.cpp", "batch.cpp", "kernels_p1.hip", "kernels_tile.hip", "kernels_util.hip", "kernels_blas.hip"]
+SOURCES = ["host.cpp", "batch.cpp", "tune_cache.cpp", "kernels_p1.hip", "kernels_tile.hip", "kernels_util.hip",
+           "kernels_blas.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-atomics",

@@ -1,14 +1,15 @@
 // Batched operators and the mixed-precision iterative-refinement CG solver.
 //
 // A batch applies many operator instances -- uneven refinement levels and
-// coefficients, vectors concatenated -- in one persistent launch of the
-// element kernel: the tile lists of all instances form one work list walked
-// by the resident workgroups, so small instances do not each pay a launch
-// and large ones do not serialise.  The solver refines an FP64 solution with
-// FP32 conjugate-gradient corrections: the outer residual b - A x, the norms
-// and the solution update are FP64, the inner CG runs the FP32 operator with
-// FP64-accumulated dot products, and a block of inner iterations is captured
-// once into a HIP graph and replayed.
+// coefficients, vectors concatenated -- in one launch of the element kernel:
+// the tile lists of all instances form one work list (largest instances
+// first), so small instances do not each pay a launch and large ones do not
+// serialise.  The solver refines an FP64 solution with conjugate-gradient
+// corrections in the inner batch's precision (FP32, or FP64 for plain FP64
+// CG): the outer residual b - A x, the norms and the solution update are
+// FP64, the inner CG runs the inner operator with FP64-accumulated dot
+// products, and a block of inner iterations is captured once into a HIP graph
+// and replayed.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -39,11 +40,12 @@ struct tmf_batch {
 };
 
 struct tmf_ir {
-  tmf_batch *b64 = nullptr, *b32 = nullptr;
+  tmf_batch *b64 = nullptr, *b32 = nullptr;  // outer (FP64) and inner (FP32 or FP64) batches
+  bool inner64 = false;                      // inner iteration in FP64 (plain FP64 CG)
   tmf_ir_options opt{};
   hipStream_t stream = nullptr;
   DevBuf<double> Ax, r64, part1, part2, scal;
-  DevBuf<float> r32, p, q, d, dinv;
+  DevBuf<uint8_t> r32, p, q, d, dinv;  // inner vectors, element type of the inner batch
   DevBuf<int> it;
   DevBuf<uint8_t> flags;
   BlasCtx ctx{};
@@ -90,8 +92,8 @@ hipError_t batch_apply_t(tmf_batch *b, int mode, const void *coeff, const void *
                                b->nseamwork[c], yy, active, 0, b->ncomp, seam_ppt(b->ops[0]), c, b->seamrows[c], s);
 }
 
-// tile shapes of a batch: epsilon has one; the scalar P2 kinds also take the marching shapes
-int batch_num_tiles(const tmf_batch *b) { return b->kind == TMF_P2V_EPSILON ? 1 : kNumTileCfg; }
+// tile shapes of a batch: epsilon has two; the scalar P2 kinds also take the marching shapes
+int batch_num_tiles(const tmf_batch *b) { return b->kind == TMF_P2V_EPSILON ? 2 : kNumTileCfg; }
 
 tmf_status batch_apply(tmf_batch *b, const void *coeff, const void *x, void *y, const uint8_t *active,
                        hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool zero_inactive = true) {
@@ -326,18 +328,61 @@ tmf_status tmf_batch_autotune(tmf_batch *b, const void *coeff, const void *x, vo
   return TMF_OK;
 }
 
+tmf_status tmf_batch_tune(tmf_batch *b, const void *coeff, const void *x, void *y, tmf_stream stream, int reps,
+                          const char *cache_json_path, int *best_cfg, float *best_ms) {
+  if (!b) return fail(TMF_EINVAL, "batch is NULL");
+  std::string key = "batch kind=" + std::to_string(b->kind) + " prec=" + std::to_string(b->prec) +
+                    " count=" + std::to_string(b->count) + " levels=";
+  for (int i = 0; i < b->count; ++i)
+    key += (i ? "," : "") + std::to_string(b->ops[i]->mesh->level) + ":" + std::to_string(b->ops[i]->mesh->nt);
+  key += " dev=" + device_tag();
+  int cfg = 0, box = 0;
+  float ms = 0;
+  if (cache_json_path) {
+    const int r = tune_cache_lookup(cache_json_path, key, &cfg, &box, &ms);
+    if (r < 0) return fail(TMF_EINVAL, "tile cache %s is not a cache file this library wrote", cache_json_path);
+    const int nt = batch_num_tiles(b);
+    if (r == 1 && cfg >= 0 && cfg < nt && box >= 0 && box < nt && kTileMarch[box] == 0) {
+      b->tile_cfg = cfg;
+      b->classic_cfg = box;
+      if (best_cfg) *best_cfg = cfg;
+      if (best_ms) *best_ms = ms;
+      return TMF_OK;
+    }
+  }
+  tmf_status st = tmf_batch_autotune(b, coeff, x, y, stream, reps, &cfg, &ms);
+  if (st == TMF_OK && cache_json_path) st = tune_cache_store(cache_json_path, key, cfg, b->classic_cfg, ms);
+  if (st != TMF_OK) return st;
+  if (best_cfg) *best_cfg = cfg;
+  if (best_ms) *best_ms = ms;
+  return TMF_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------------ solver
 namespace {
 
-tmf_status inner_step(tmf_ir *S, const void *k32, hipStream_t s) {
+template <typename V>
+V *vec(DevBuf<uint8_t> &b) {
+  return reinterpret_cast<V *>(b.p);
+}
+
+// one inner iteration; par = parity of the iteration within its block (the
+// slot of r.z it reads)
+template <typename V>
+tmf_status inner_step_t(tmf_ir *S, const void *k32, int par, hipStream_t s) {
   tmf_status st = batch_apply(S->b32, k32, S->p.p, S->q.p, S->ctx.sc.iact, s, nullptr, nullptr, false);
   if (st != TMF_OK) return st;
-  hipError_t e = blas_cg_step_after_apply(S->ctx, S->d.p, S->r32.p, S->p.p, S->q.p, S->part1.p,
-                                          S->opt.inner_rtol * S->opt.inner_rtol, S->opt.inner_maxit, s);
+  hipError_t e = blas_cg_step_after_apply<V>(S->ctx, vec<V>(S->d), vec<V>(S->r32), vec<V>(S->p), vec<V>(S->q),
+                                             S->part1.p, S->part2.p, S->opt.inner_rtol * S->opt.inner_rtol,
+                                             S->opt.inner_maxit, par, s);
   if (e != hipSuccess) return hip_fail(e, "CG step launch");
   return TMF_OK;
+}
+
+tmf_status inner_step(tmf_ir *S, const void *k32, int par, hipStream_t s) {
+  return S->inner64 ? inner_step_t<double>(S, k32, par, s) : inner_step_t<float>(S, k32, par, s);
 }
 
 tmf_status capture(tmf_ir *S, const void *k32) {
@@ -352,7 +397,7 @@ tmf_status capture(tmf_ir *S, const void *k32) {
   hipError_t e = hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
   tmf_status st = TMF_OK;
-  for (int i = 0; i < S->opt.graph_iters && st == TMF_OK; ++i) st = inner_step(S, k32, S->stream);
+  for (int i = 0; i < S->opt.graph_iters && st == TMF_OK; ++i) st = inner_step(S, k32, i & 1, S->stream);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(S->stream, &g);
   if (st != TMF_OK) {
@@ -375,35 +420,37 @@ tmf_status tmf_ir_create(tmf_batch *b64, tmf_batch *b32, const tmf_ir_options *o
   if (!out) return fail(TMF_EINVAL, "out is NULL");
   *out = nullptr;
   if (!b64 || !b32) return fail(TMF_EINVAL, "both batches are required");
-  if (b64->prec != TMF_F64 || b32->prec != TMF_F32) return fail(TMF_EINVAL, "need an FP64 and an FP32 batch");
+  if (b64->prec != TMF_F64) return fail(TMF_EINVAL, "the outer batch must be FP64");
   if (b64->count != b32->count || b64->kind != b32->kind) return fail(TMF_EINVAL, "batches do not match");
   for (int i = 0; i < b64->count; ++i)
     if (b64->ops[i]->mesh != b32->ops[i]->mesh || b64->ops[i]->bc != b32->ops[i]->bc)
       return fail(TMF_EINVAL, "instance %d differs between the batches", i);
   if (b64->ncomp != 1) return fail(TMF_EUNSUPPORTED, "the solver handles scalar operators");
   tmf_ir_options o = opt ? *opt : tmf_ir_options{1e-10, 30, 1e-4, 2000, 16, 1, TMF_PRECOND_JACOBI};
-  if (!(o.tol > 0) || o.max_outer < 1 || !(o.inner_rtol > 0) || o.inner_maxit < 1 || o.graph_iters < 1 ||
-      (o.precond != TMF_PRECOND_NONE && o.precond != TMF_PRECOND_JACOBI))
-    return fail(TMF_EINVAL, "bad solver options");
+  if (!(o.tol > 0) || o.max_outer < 1 || !(o.inner_rtol > 0) || o.inner_maxit < 1 || o.graph_iters < 2 ||
+      (o.graph_iters & 1) || (o.precond != TMF_PRECOND_NONE && o.precond != TMF_PRECOND_JACOBI))
+    return fail(TMF_EINVAL, "bad solver options (graph_iters must be even and at least 2)");
   if (o.precond == TMF_PRECOND_JACOBI && b64->kind != TMF_P2_LAPLACE && b64->kind != TMF_P2_DIVKGRAD)
     return fail(TMF_EUNSUPPORTED, "the Jacobi preconditioner needs a scalar P2 kind");
   auto *S = new (std::nothrow) tmf_ir;
   if (!S) return fail(TMF_ENOMEM, "host allocation failed");
   S->b64 = b64;
   S->b32 = b32;
+  S->inner64 = b32->prec == TMF_F64;
   S->opt = o;
   const int64_t n = b64->off[b64->count];
+  const size_t vb = static_cast<size_t>(n) * (S->inner64 ? 8 : 4);
   const int c = b64->count;
   tmf_status st = S->Ax.alloc(n);
   if (st == TMF_OK) st = S->r64.alloc(n);
-  if (st == TMF_OK) st = S->r32.alloc(n);
-  if (st == TMF_OK) st = S->p.alloc(n);
-  if (st == TMF_OK) st = S->q.alloc(n);
-  if (st == TMF_OK) st = S->d.alloc(n);
-  if (st == TMF_OK && o.precond == TMF_PRECOND_JACOBI) st = S->dinv.alloc(n);
+  if (st == TMF_OK) st = S->r32.alloc(vb);
+  if (st == TMF_OK) st = S->p.alloc(vb);
+  if (st == TMF_OK) st = S->q.alloc(vb);
+  if (st == TMF_OK) st = S->d.alloc(vb);
+  if (st == TMF_OK && o.precond == TMF_PRECOND_JACOBI) st = S->dinv.alloc(vb);
   if (st == TMF_OK) st = S->part1.alloc(b64->nchunks);
   if (st == TMF_OK) st = S->part2.alloc(b64->nchunks);
-  if (st == TMF_OK) st = S->scal.alloc(6 * static_cast<size_t>(c));
+  if (st == TMF_OK) st = S->scal.alloc(7 * static_cast<size_t>(c));
   if (st == TMF_OK) st = S->it.alloc(c);
   if (st == TMF_OK) st = S->flags.alloc(2 * static_cast<size_t>(c));
   if (st == TMF_OK) {
@@ -413,7 +460,8 @@ tmf_status tmf_ir_create(tmf_batch *b64, tmf_batch *b32, const tmf_ir_options *o
   if (st == TMF_OK) {
     // one eager FP32 apply on the zeroed workspace: initialises the launch
     // configuration outside any graph capture
-    hipError_t e = launch_fill<float>(S->p.p, n, 0.0f, S->stream);
+    hipError_t e = S->inner64 ? launch_fill<double>(vec<double>(S->p), n, 0.0, S->stream)
+                              : launch_fill<float>(vec<float>(S->p), n, 0.0f, S->stream);
     if (e != hipSuccess) st = hip_fail(e, "workspace fill");
     if (st == TMF_OK) st = batch_apply(b32, has_coeff(b32->kind) ? S->p.p : nullptr, S->p.p, S->q.p, nullptr, S->stream);
     if (st == TMF_OK && (e = hipStreamSynchronize(S->stream)) != hipSuccess) st = hip_fail(e, "warm-up");
@@ -431,10 +479,11 @@ tmf_status tmf_ir_create(tmf_batch *b64, tmf_batch *b32, const tmf_ir_options *o
   x.dinv = o.precond == TMF_PRECOND_JACOBI ? S->dinv.p : nullptr;
   x.sc.rnorm = S->scal.p;
   x.sc.bnorm = S->scal.p + c;
-  x.sc.rr = S->scal.p + 2 * c;
-  x.sc.rr0 = S->scal.p + 3 * c;
-  x.sc.alpha = S->scal.p + 4 * c;
-  x.sc.beta = S->scal.p + 5 * c;
+  x.sc.rr = S->scal.p + 2 * c;  // two slots
+  x.sc.rr0 = S->scal.p + 4 * c;
+  x.sc.alpha = S->scal.p + 5 * c;
+  x.sc.beta = S->scal.p + 6 * c;
+  x.sc.count = c;
   x.sc.it = S->it.p;
   x.sc.oact = S->flags.p;
   x.sc.iact = S->flags.p + c;
@@ -444,7 +493,7 @@ tmf_status tmf_ir_create(tmf_batch *b64, tmf_batch *b32, const tmf_ir_options *o
 
 void tmf_ir_destroy(tmf_ir *s) { delete s; }
 
-tmf_status tmf_ir_solve(tmf_ir *S, const double *coeff64, const float *coeff32, const double *b, double *x,
+tmf_status tmf_ir_solve(tmf_ir *S, const double *coeff64, const void *coeff32, const double *b, double *x,
                         tmf_ir_stats *stats, double *relres, tmf_stream stream) {
   if (!S) return fail(TMF_EINVAL, "solver is NULL");
   if (!b || !x || x == b) return fail(TMF_EINVAL, "b and x are required and must differ");
@@ -466,7 +515,8 @@ tmf_status tmf_ir_solve(tmf_ir *S, const double *coeff64, const float *coeff32, 
   if (S->opt.precond == TMF_PRECOND_JACOBI) {
     tmf_status sd = batch_diagonal(S->b64, coeff64, S->Ax.p, s);
     if (sd != TMF_OK) return sd;
-    e = blas_inverse_diagonal(S->ctx, S->Ax.p, S->dinv.p, s);
+    e = S->inner64 ? blas_inverse_diagonal<double>(S->ctx, S->Ax.p, vec<double>(S->dinv), s)
+                   : blas_inverse_diagonal<float>(S->ctx, S->Ax.p, vec<float>(S->dinv), s);
     if (e != hipSuccess) return hip_fail(e, "inverse diagonal");
   }
   std::vector<uint8_t> flags(2 * c);
@@ -496,7 +546,10 @@ tmf_status tmf_ir_solve(tmf_ir *S, const double *coeff64, const float *coeff32, 
     }
     if (outer == S->opt.max_outer) break;
     st_out.outer = outer + 1;
-    e = blas_start_inner(S->ctx, S->r64.p, S->r32.p, S->p.p, S->d.p, S->part1.p, s);
+    e = S->inner64 ? blas_start_inner<double>(S->ctx, S->r64.p, vec<double>(S->r32), vec<double>(S->p),
+                                              vec<double>(S->d), S->part1.p, s)
+                   : blas_start_inner<float>(S->ctx, S->r64.p, vec<float>(S->r32), vec<float>(S->p),
+                                             vec<float>(S->d), S->part1.p, s);
     if (e != hipSuccess) {
       st = hip_fail(e, "inner start");
       break;
@@ -514,7 +567,7 @@ tmf_status tmf_ir_solve(tmf_ir *S, const double *coeff64, const float *coeff32, 
         }
         st_out.graph_launches++;
       } else {
-        for (int i = 0; i < S->opt.graph_iters && st == TMF_OK; ++i) st = inner_step(S, coeff32, s);
+        for (int i = 0; i < S->opt.graph_iters && st == TMF_OK; ++i) st = inner_step(S, coeff32, i & 1, s);
         if (st != TMF_OK) break;
       }
       e = hipMemcpyAsync(flags.data() + c, S->flags.p + c, c, hipMemcpyDeviceToHost, s);
@@ -532,7 +585,8 @@ tmf_status tmf_ir_solve(tmf_ir *S, const double *coeff64, const float *coeff32, 
     int itmax = 0;
     for (int i = 0; i < c; ++i) itmax = std::max(itmax, its[i]);
     st_out.inner_total += itmax;
-    e = blas_update_x(S->ctx, x, S->d.p, s);
+    e = S->inner64 ? blas_update_x<double>(S->ctx, x, vec<double>(S->d), s)
+                   : blas_update_x<float>(S->ctx, x, vec<float>(S->d), s);
     if (e != hipSuccess) st = hip_fail(e, "solution update");
   }
   if (st == TMF_OK) {

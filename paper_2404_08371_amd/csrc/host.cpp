@@ -860,20 +860,47 @@ tmf_status tmf_apply_local(tmf_op *op, const void *coeff, const void *x, void *y
   return TMF_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// diag(A) of a P1 kind: one vertex-centric launch, then the interface sum
+template <typename T>
+hipError_t p1_diagonal(tmf_op *op, const void *coeff, void *d, hipStream_t s) {
+  P1Args<T> a;
+  a.lat = lattice_args<T>(op);
+  a.w15 = reinterpret_cast<const T *>(op->w15.p);
+  a.k = static_cast<const T *>(coeff);
+  a.x = nullptr;
+  a.y = static_cast<T *>(d);
+  hipError_t e = launch_p1_apply<T>(a, op->kind == TMF_P1_LAPLACE ? P1_LAPLACE_DIAG : P1_DIVKGRAD_DIAG,
+                                    op->chunks.p, op->nchunks, s);
+  if (e != hipSuccess) return e;
+  return launch_interface_sum<T>(group_args(op), static_cast<T *>(d), s);
+}
+}  // namespace
+
+extern "C" {
+
 tmf_status tmf_diagonal(tmf_op *op, const void *coeff, void *d, tmf_stream stream) {
   if (!op || !d) return fail(TMF_EINVAL, "op or d is NULL");
-  if ((op->kind != TMF_P2_LAPLACE && op->kind != TMF_P2_DIVKGRAD) || op->nq > 0)
-    return fail(TMF_EUNSUPPORTED, "the diagonal is provided for the exactly integrated scalar P2 kinds");
+  if (op->kind == TMF_N1_CURLCURL || (op->nq > 0 && op->kind != TMF_P2V_EPSILON))
+    return fail(TMF_EUNSUPPORTED, "the diagonal is provided for the P1, exact scalar P2 and epsilon kinds");
   if (has_coeff(op->kind) != (coeff != nullptr))
     return fail(TMF_EINVAL, has_coeff(op->kind) ? "this operator needs a coefficient field"
                                                 : "this operator takes no coefficient field");
   if (coeff && d == coeff) return fail(TMF_EINVAL, "d must not alias the coefficient");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int dk = op->kind == TMF_P2_LAPLACE ? P2_LAPLACE_DIAG : P2_DIVKGRAD_DIAG;
-  // the diagonal modes read no x; the output pointer stands in for it
-  hipError_t e = op->prec == TMF_F64
-                     ? tile_path<double>(op, dk, coeff, d, static_cast<double *>(d), s, nullptr, nullptr, true)
-                     : tile_path<float>(op, dk, coeff, d, static_cast<float *>(d), s, nullptr, nullptr, true);
+  hipError_t e;
+  if (op->space == 1) {
+    e = op->prec == TMF_F64 ? p1_diagonal<double>(op, coeff, d, s) : p1_diagonal<float>(op, coeff, d, s);
+  } else {
+    const int dk = op->kind == TMF_P2_LAPLACE   ? P2_LAPLACE_DIAG
+                   : op->kind == TMF_P2_DIVKGRAD ? P2_DIVKGRAD_DIAG
+                                                 : P2V_EPSILON_DIAG;
+    // the diagonal modes read no x; the output pointer stands in for it
+    e = op->prec == TMF_F64 ? tile_path<double>(op, dk, coeff, d, static_cast<double *>(d), s, nullptr, nullptr, true)
+                            : tile_path<float>(op, dk, coeff, d, static_cast<float *>(d), s, nullptr, nullptr, true);
+  }
   if (e != hipSuccess) return hip_fail(e, "diagonal launch");
   return TMF_OK;
 }
@@ -930,7 +957,7 @@ tmf_status tmf_interface_sum(tmf_op *op, void *v, tmf_stream stream) {
 
 static int num_tiles(const tmf_op *op) {
   if (op->space == 1) return 1;
-  if (op->kind == TMF_P2V_EPSILON) return 1;
+  if (op->kind == TMF_P2V_EPSILON) return 2;
   // the marching shapes serve the exactly integrated scalar P2 applies
   const bool march = (op->kind == TMF_P2_LAPLACE || op->kind == TMF_P2_DIVKGRAD) && op->nq == 0;
   return march ? kNumTileCfg : kNumClassicTileCfg;
@@ -1011,6 +1038,34 @@ tmf_status tmf_op_autotune(tmf_op *op, const void *coeff, const void *x, void *y
   op->classic_cfg = best_box;
   if (best_cfg) *best_cfg = best;
   if (best_ms) *best_ms = best_t;
+  return TMF_OK;
+}
+
+tmf_status tmf_op_tune(tmf_op *op, const void *coeff, const void *x, void *y, tmf_stream stream, int reps,
+                       const char *cache_json_path, int *best_cfg, float *best_ms) {
+  if (!op) return fail(TMF_EINVAL, "op is NULL");
+  char key[256];
+  std::snprintf(key, sizeof(key), "op kind=%d prec=%d bc=%d nq=%d map=%d level=%d macros=%lld dev=%s", op->kind,
+                op->prec, op->bc, op->nq, op->mesh->map, op->mesh->level, static_cast<long long>(op->mesh->nt),
+                device_tag().c_str());
+  int cfg = 0, box = 0;
+  float ms = 0;
+  if (cache_json_path) {
+    const int r = tune_cache_lookup(cache_json_path, key, &cfg, &box, &ms);
+    if (r < 0) return fail(TMF_EINVAL, "tile cache %s is not a cache file this library wrote", cache_json_path);
+    if (r == 1 && cfg >= 0 && cfg < num_tiles(op) && box >= 0 && box < num_tiles(op) && kTileMarch[box] == 0) {
+      op->tile_cfg = cfg;
+      op->classic_cfg = box;
+      if (best_cfg) *best_cfg = cfg;
+      if (best_ms) *best_ms = ms;
+      return TMF_OK;
+    }
+  }
+  tmf_status st = tmf_op_autotune(op, coeff, x, y, stream, reps, &cfg, &ms);
+  if (st == TMF_OK && cache_json_path) st = tune_cache_store(cache_json_path, key, cfg, op->classic_cfg, ms);
+  if (st != TMF_OK) return st;
+  if (best_cfg) *best_cfg = cfg;
+  if (best_ms) *best_ms = ms;
   return TMF_OK;
 }
 

@@ -180,6 +180,12 @@ InstDesc<T> make_desc(const tmf_op *op, int64_t off) {
 
 
 namespace tmf {
+// autotuner cache (tune_cache.cpp): device tag "<arch>/<CUs>cu"; lookup returns
+// 1 (found: cfg, box shape and time set), 0 (not found) or -1 (unreadable file)
+std::string device_tag();
+int tune_cache_lookup(const char *path, const std::string &key, int *cfg, int *box, float *ms);
+tmf_status tune_cache_store(const char *path, const std::string &key, int cfg, int box, float ms);
+
 inline bool has_coeff(int kind) {
   return kind == TMF_P1_DIVKGRAD || kind == TMF_P2_DIVKGRAD || kind == TMF_P2V_EPSILON || kind == TMF_N1_CURLCURL;
 }

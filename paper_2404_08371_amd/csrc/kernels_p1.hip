@@ -123,6 +123,37 @@ __device__ __forceinline__ T p1k_row(GeoPtr<T> g, const T X[3][7], const T K[3][
   return acc;
 }
 
+// diagonal entry of row p: sum over the existing micro-tets containing p of
+// kbar_T (Gp_T)_aa, with (Gp_T)_aa = -sum_{c != a} (Gp_T)_ac (zero row sums)
+template <typename T, int t, int a>
+__device__ __forceinline__ void p1k_diag_tet(GeoPtr<T> g, const T K[3][7], int z, T &acc) {
+  T gaa = T(0);
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if (c != a) gaa -= goff(g, t, a, c);
+  const int q0 = kVS.v[t][a][0], q1 = kVS.v[t][a][1], q2 = kVS.v[t][a][2], q3 = kVS.v[t][a][3];
+  const T kb = (nbval(K, q0) + nbval(K, q1) + nbval(K, q2) + nbval(K, q3)) * T(0.25);
+  acc += tet_exists<t, a>(z) ? kb * gaa : T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ T p1k_diag(GeoPtr<T> g, const T K[3][7], int z) {
+  T acc = T(0);
+  p1k_diag_tet<T, 0, 0>(g, K, z, acc); p1k_diag_tet<T, 0, 1>(g, K, z, acc);
+  p1k_diag_tet<T, 0, 2>(g, K, z, acc); p1k_diag_tet<T, 0, 3>(g, K, z, acc);
+  p1k_diag_tet<T, 1, 0>(g, K, z, acc); p1k_diag_tet<T, 1, 1>(g, K, z, acc);
+  p1k_diag_tet<T, 1, 2>(g, K, z, acc); p1k_diag_tet<T, 1, 3>(g, K, z, acc);
+  p1k_diag_tet<T, 2, 0>(g, K, z, acc); p1k_diag_tet<T, 2, 1>(g, K, z, acc);
+  p1k_diag_tet<T, 2, 2>(g, K, z, acc); p1k_diag_tet<T, 2, 3>(g, K, z, acc);
+  p1k_diag_tet<T, 3, 0>(g, K, z, acc); p1k_diag_tet<T, 3, 1>(g, K, z, acc);
+  p1k_diag_tet<T, 3, 2>(g, K, z, acc); p1k_diag_tet<T, 3, 3>(g, K, z, acc);
+  p1k_diag_tet<T, 4, 0>(g, K, z, acc); p1k_diag_tet<T, 4, 1>(g, K, z, acc);
+  p1k_diag_tet<T, 4, 2>(g, K, z, acc); p1k_diag_tet<T, 4, 3>(g, K, z, acc);
+  p1k_diag_tet<T, 5, 0>(g, K, z, acc); p1k_diag_tet<T, 5, 1>(g, K, z, acc);
+  p1k_diag_tet<T, 5, 2>(g, K, z, acc); p1k_diag_tet<T, 5, 3>(g, K, z, acc);
+  return acc;
+}
+
 // 1/4 (D gy)_T . Gp_T (D x)_T summed over the existing micro-tets containing p
 // (DR, DX centred gy and x)
 template <typename T, int t, int a>
@@ -292,9 +323,11 @@ __device__ __forceinline__ Unit unit_of(const int4 *__restrict__ units, int nuni
 }
 constexpr int kUnitPoints = 62;  // output points per wavefront row
 
+// KIND P1_DIVKGRAD: y = A(k) x; P1_DIVKGRAD_DIAG: y = diag(A(k)) (no x read)
 template <typename T, int KIND>
 __global__ __launch_bounds__(256) void k_p1_apply(P1Args<T> a, const int4 *__restrict__ units, int nunits) {
-  constexpr bool VARK = KIND == P1_DIVKGRAD;
+  constexpr bool VARK = KIND == P1_DIVKGRAD || KIND == P1_DIVKGRAD_DIAG;
+  constexpr bool DIAG = KIND == P1_DIVKGRAD_DIAG;
   const LatticeArgs<T> &L = a.lat;
   const Unit U = unit_of(units, nunits);
   // the macro's 16 boundary-class stencils (all units of a workgroup share
@@ -325,24 +358,28 @@ __global__ __launch_bounds__(256) void k_p1_apply(P1Args<T> a, const int4 *__res
   constexpr int PD = VARK ? 1 : 2;
   Window<T> X, K;
   T nx[PD][3], nk[PD][3];
-  window_init<T, true>(X, x, i, U.j0, k, N, dm);
+  if (!DIAG) window_init<T, true>(X, x, i, U.j0, k, N, dm);
   if (VARK) window_init<T, false>(K, kc, i, U.j0, k, N, 0u);
 #pragma unroll
   for (int b = 0; b < PD; ++b) {
-    window_next<T, true>(nx[b], x, i, U.j0 + b, k, N, dm);
+    if (!DIAG) window_next<T, true>(nx[b], x, i, U.j0 + b, k, N, dm);
     if (VARK) window_next<T, false>(nk[b], kc, i, U.j0 + b, k, N, 0u);
   }
   auto step = [&](int j, T(&nxb)[3], T(&nkb)[3]) {
-    window_enter(X, nxb);
+    if (!DIAG) window_enter(X, nxb);
     if (VARK) window_enter(K, nkb);
-    window_next<T, true>(nxb, x, i, j + PD, k, N, dm);
+    if (!DIAG) window_next<T, true>(nxb, x, i, j + PD, k, N, dm);
     if (VARK) window_next<T, false>(nkb, kc, i, j + PD, k, N, 0u);
     T PX[3][7];
-    neighbourhood(X, PX);
+    if (!DIAG) neighbourhood(X, PX);
     const int z = zero_pattern(i, j, k, N);
     const bool out = out_lane && i <= N - j - k;
     T acc = T(0);
-    if (VARK) {
+    if (DIAG) {
+      T PK[3][7];
+      neighbourhood(K, PK);
+      acc = p1k_diag(g, PK, z);
+    } else if (VARK) {
       T PK[3][7];
       neighbourhood(K, PK);
       acc = p1k_row(g, PX, PK, z);
@@ -357,7 +394,7 @@ __global__ __launch_bounds__(256) void k_p1_apply(P1Args<T> a, const int4 *__res
     }
     if ((dm >> z) & 1u) acc = T(0);
     buf_store(acc, y, point_off<T>(out, i, j, k, N));
-    window_slide(X);
+    if (!DIAG) window_slide(X);
     if (VARK) window_slide(K);
   };
   for (int j = U.j0; j < U.j1; j += PD) {
@@ -444,6 +481,32 @@ __global__ __launch_bounds__(256) void k_p1_stencil(P1Args<T> a, const int4 *__r
   }
 }
 
+// Diagonal of the constant-coefficient operator: the centre weight of the
+// point's boundary-class stencil (0 on Dirichlet rows), over the stencil
+// tiles of k_p1_stencil
+template <typename T>
+__global__ __launch_bounds__(256) void k_p1_stencil_diag(P1Args<T> a, const int4 *__restrict__ units, int nunits) {
+  const LatticeArgs<T> &L = a.lat;
+  const Unit U0 = unit_of(units, nunits);
+  if (!U0.valid) return;
+  const int j0 = U0.k, i0 = U0.i0, k0 = U0.j0, k1 = U0.j1;
+  const int N = L.N, lane = threadIdx.x & 63, i = i0 - 1 + lane;
+  const int64_t base = static_cast<int64_t>(U0.m) * L.L;
+  const uint32_t dm = L.dirichlet ? L.bnd[U0.m] : 0u;
+  const Rsrc y = block_rsrc(a.y + base, L.L);
+  const bool out_lane = lane >= 1 && lane <= kUnitPoints;
+  const auto *w = (const __attribute__((address_space(4))) T *)(a.w15 + 16 * 15 * U0.m);
+  for (int k = k0; k < k1; ++k)
+#pragma unroll
+    for (int r = 0; r < KJ; ++r) {
+      const int j = j0 + r;
+      const bool out = out_lane && i >= 0 && j + k <= N && i <= N - j - k;
+      const int z = out ? zero_pattern(i, j, k, N) : 0;
+      const T d = ((dm >> z) & 1u) ? T(0) : w[15 * z];
+      buf_store(d, y, point_off<T>(out, i, j, k, N));
+    }
+}
+
 // Fused reverse mode of the macro-local P1 div(k grad) apply:
 //   gx_p = (L(k) gy)_p,  gk_p = sum_{T containing p} 1/4 (D gy)_T . Gp_T (D x)_T
 template <typename T>
@@ -498,10 +561,15 @@ __global__ __launch_bounds__(256) void k_p1_adjoint(P1AdjArgs<T> a, const int4 *
 template <typename T>
 hipError_t launch_p1_apply(const P1Args<T> &a, int kind, const int4 *units, int nunits, hipStream_t s) {
   const dim3 grid(((nunits + 3) / 4) * a.lat.nt);
-  if (kind == P1_LAPLACE)
-    hipLaunchKernelGGL((k_p1_stencil<T>), grid, dim3(256), 0, s, a, units, nunits);
-  else
-    hipLaunchKernelGGL((k_p1_apply<T, P1_DIVKGRAD>), grid, dim3(256), 0, s, a, units, nunits);
+  switch (kind) {
+    case P1_LAPLACE: hipLaunchKernelGGL((k_p1_stencil<T>), grid, dim3(256), 0, s, a, units, nunits); break;
+    case P1_DIVKGRAD: hipLaunchKernelGGL((k_p1_apply<T, P1_DIVKGRAD>), grid, dim3(256), 0, s, a, units, nunits); break;
+    case P1_LAPLACE_DIAG: hipLaunchKernelGGL((k_p1_stencil_diag<T>), grid, dim3(256), 0, s, a, units, nunits); break;
+    case P1_DIVKGRAD_DIAG:
+      hipLaunchKernelGGL((k_p1_apply<T, P1_DIVKGRAD_DIAG>), grid, dim3(256), 0, s, a, units, nunits);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

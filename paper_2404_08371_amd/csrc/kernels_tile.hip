@@ -739,6 +739,16 @@ constexpr int n1_edge_sign(int t, int e) {
   return d[0] != 0 ? (d[0] > 0 ? 1 : -1) : d[1] != 0 ? (d[1] > 0 ? 1 : -1) : (d[2] > 0 ? 1 : -1);
 }
 
+// LDS barrier without a wait on global memory (buffer-to-LDS loads and
+// global stores stay in flight): the fences order LDS accesses only
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+// wait for this wavefront's vector memory operations (vmcnt(0); LDS counter untouched)
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 template <typename T, int KIND, int MAP, int TX, int TY, int TZ>
 struct TileCfg {
   static constexpr int RX = 2 * TX + 1, RY = 2 * TY + 1, RZ = 2 * TZ + 1;
@@ -755,17 +765,17 @@ struct TileCfg {
   static_assert(TX == 4 || TX == 8, "row pitch chosen for TX = 4 or 8");
   static_assert(RXP >= OO + TX && (2 * RXP - TX) % 16 == 0, "row pitch");
   static constexpr int C = TX * TY * TZ;
-  static constexpr bool EPS = KIND == P2V_EPSILON || KIND == P2V_EPSILON_GRADMU;  // vector element
-  static constexpr int NC = KIND == P2V_EPSILON ? 3 : 1;  // output components
-  // diagonal mode: no x is staged, each micro-tet adds its local diagonal
-  static constexpr bool DIAG = KIND == P2_LAPLACE_DIAG || KIND == P2_DIVKGRAD_DIAG;
+  static constexpr bool EPS = KIND == P2V_EPSILON || KIND == P2V_EPSILON_GRADMU || KIND == P2V_EPSILON_DIAG;
+  static constexpr int NC = (KIND == P2V_EPSILON || KIND == P2V_EPSILON_DIAG) ? 3 : 1;  // output components
+  // diagonal modes: no x is staged, each micro-tet adds its local diagonal
+  static constexpr bool DIAG = KIND == P2_LAPLACE_DIAG || KIND == P2_DIVKGRAD_DIAG || KIND == P2V_EPSILON_DIAG;
   // coefficient-gradient modes: x and gy staged (both masked), no coefficient;
   // the output gk is not zeroed on Dirichlet DoFs (boundary values of k act
   // on interior rows)
   static constexpr bool GRADK = KIND == P2_DIVKGRAD_GRADK, GRADMU = KIND == P2V_EPSILON_GRADMU;
   static constexpr bool GRAD = GRADK || GRADMU;
   static constexpr int NCX = GRADMU ? 3 : GRADK ? 1 : NC;   // components of x
-  static constexpr int NCI = GRAD ? 2 * NCX : NC;           // staged input vectors (x, then gy)
+  static constexpr int NCI = DIAG ? 1 : GRAD ? 2 * NCX : NC;  // staged input vectors (x, then gy; diagonal: none used)
   static constexpr bool HASK = KIND != P2_LAPLACE && KIND != P2_LAPLACE_DIAG && !GRAD && KIND != P2_STORED_APPLY;
   // N1: edge DoFs with a per-slot orientation sign; two coefficients (alpha,
   // beta) read at the vertex points
@@ -792,10 +802,38 @@ struct TileCfg {
 };
 
 // one micro-tet whose 10 local nodes sit at LDS points li[]
+// The stored element matrices of one (tile, type): entry e of cube c at
+// element e * C + c.  A buffer resource over the block keeps the 55 entry
+// offsets as scalar offsets of one per-lane offset, instead of 55 64-bit
+// addresses held in vector registers.
+struct MatRef {
+  __amdgpu_buffer_rsrc_t r;
+  int off;  // byte offset of this lane's cube
+};
+template <typename T>
+__device__ __forceinline__ T mat_load(const MatRef &m, int e) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(m.r, m.off, e * 8, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(m.r, m.off, e * 4, 0));
+}
+template <typename T>
+__device__ __forceinline__ void mat_store(const MatRef &m, int e, T v) {
+  typedef unsigned int U2 __attribute__((ext_vector_type(2)));
+  if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), m.r, m.off, e * 8, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), m.r, m.off, e * 4, 0);
+}
+
+// one micro-tet whose 10 local nodes sit at LDS points li[]: its local
+// results go to out[] (out[10 c + v] for component c at node v; N1 uses
+// out[4 .. 9] for its edges), added into the accumulator later in a fixed
+// order (cube_scatter)
 template <typename T, int KIND, int MAP, int R, int t, int CS>
 __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T> *D, T (*sx)[R], const T *sk,
-                                          double (*sy)[R], const int li[10], int m, int bxc, int byc, int bzc,
-                                          GPtr<T> me) {
+                                          T *out, const int li[10], int m, int bxc, int byc, int bzc,
+                                          const MatRef &me) {
   const TypeGeo<T> *g = D->geo + 6 * m + t;
   if constexpr (KIND == P2V_EPSILON) {
     T u[3][10], mu[10], y[3][10];
@@ -823,7 +861,48 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
 #pragma unroll
     for (int v = 0; v < 10; ++v)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) atomicAdd(&sy[c][li[v]], double(y[c][v]));
+      for (int c = 0; c < 3; ++c) out[10 * c + v] = y[c][v];
+  } else if constexpr (KIND == P2V_EPSILON_DIAG) {
+    // the 30 diagonal entries (A_T)_(v,c),(v,c): the element applied to each
+    // unit vector in turn (a runtime loop, so the element code is emitted
+    // once), entry (v, c) of the result kept
+    T mu[10];
+#pragma unroll
+    for (int v = 0; v < 10; ++v) mu[v] = sk[li[v]];
+#pragma unroll
+    for (int e = 0; e < 30; ++e) out[e] = T(0);
+    T P0[3] = {T(0), T(0), T(0)}, sv[3] = {T(0), T(0), T(0)};
+    if constexpr (MAP != 0) {
+      const __attribute__((address_space(4))) MacroGeo<T> &mg =
+          *(const __attribute__((address_space(4))) MacroGeo<T> *)(D->mgeo + m);
+      const T bc[3] = {T(bxc + kOff[t][0][0]), T(byc + kOff[t][0][1]), T(bzc + kOff[t][0][2])};
+      const T inv_n = T(1) / T(D->n);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        P0[d] = mg.v0[d] + (mg.JM[3 * d + 0] * bc[0] + mg.JM[3 * d + 1] * bc[1] + mg.JM[3 * d + 2] * bc[2]) * inv_n;
+        sv[d] = mg.s[d];
+      }
+    }
+#pragma unroll 1
+    for (int idx = 0; idx < 30; ++idx) {
+      T u[3][10], y[3][10];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int v = 0; v < 10; ++v) u[c][v] = (10 * c + v == idx) ? T(1) : T(0);
+      if constexpr (MAP == 0) {
+        eps_elem(u, mu, cptr(g->grad), *cptr(&g->vol), y);
+      } else {
+        eps_blended_elem(u, mu, P0, cptr(g->JT), cptr(g->grad), *cptr(&g->vol), sv, cptr(a.qtab), a.nq, y);
+      }
+      T dv = T(0);
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int v = 0; v < 10; ++v) dv += u[c][v] * y[c][v];
+#pragma unroll
+      for (int e = 0; e < 30; ++e) out[e] = e == idx ? dv : out[e];
+    }
   } else if constexpr (KIND == P2_DIVKGRAD_Q) {
     T u[10], kv[10], y[10], W[4][4];
 #pragma unroll
@@ -834,7 +913,7 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
     weights_quad(kv, cptr(a.qtab), a.nq, W);
     p2_elem_w(u, W, cptr(g->Gp), y);
 #pragma unroll
-    for (int v = 0; v < 10; ++v) atomicAdd(&sy[0][li[v]], double(y[v]));
+    for (int v = 0; v < 10; ++v) out[v] = y[v];
   } else if constexpr (KIND == P2_DIVKGRAD_STORE) {
     // columns A e_v of the local matrix; the upper triangle is stored
     T kv[10], A[10][10];
@@ -851,7 +930,7 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
 #pragma unroll
     for (int i = 0; i < 10; ++i)
 #pragma unroll
-      for (int j = i; j < 10; ++j) me[(e++) * CS] = A[j][i];
+      for (int j = i; j < 10; ++j) mat_store<T>(me, (e++) * CS, A[j][i]);
   } else if constexpr (KIND == P2_STORED_APPLY) {
     T u[10], y[10];
 #pragma unroll
@@ -864,12 +943,12 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
     for (int i = 0; i < 10; ++i)
 #pragma unroll
       for (int j = i; j < 10; ++j) {
-        const T aij = me[(e++) * CS];
+        const T aij = mat_load<T>(me, (e++) * CS);
         y[i] += aij * u[j];
         if (j != i) y[j] += aij * u[i];
       }
 #pragma unroll
-    for (int v = 0; v < 10; ++v) atomicAdd(&sy[0][li[v]], double(y[v]));
+    for (int v = 0; v < 10; ++v) out[v] = y[v];
   } else if constexpr (KIND == N1_CURLCURL) {
     T u[6], al[4], be[4], y6[6];
 #pragma unroll
@@ -881,7 +960,7 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
     }
     n1_elem(u, al, be, cptr(g->grad), *cptr(&g->vol), y6);
 #pragma unroll
-    for (int e = 0; e < 6; ++e) atomicAdd(&sy[0][li[4 + e]], double(T(n1_edge_sign(t, e)) * y6[e]));
+    for (int e = 0; e < 6; ++e) out[4 + e] = T(n1_edge_sign(t, e)) * y6[e];
   } else if constexpr (KIND == P2V_EPSILON_GRADMU) {
     T u[3][10], gv[3][10], gm[10];
 #pragma unroll
@@ -906,7 +985,7 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
       eps_blended_gradmu(u, gv, P0, cptr(g->JT), cptr(g->grad), *cptr(&g->vol), sv, cptr(a.qtab), a.nq, gm);
     }
 #pragma unroll
-    for (int v = 0; v < 10; ++v) atomicAdd(&sy[0][li[v]], double(gm[v]));
+    for (int v = 0; v < 10; ++v) out[v] = gm[v];
   } else if constexpr (KIND == P2_DIVKGRAD_GRADK) {
     T u[10], gv[10], gk[10];
 #pragma unroll
@@ -916,7 +995,7 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
     }
     p2_gradk<T>(u, gv, cptr(g->Gp), gk);
 #pragma unroll
-    for (int v = 0; v < 10; ++v) atomicAdd(&sy[0][li[v]], double(gk[v]));
+    for (int v = 0; v < 10; ++v) out[v] = gk[v];
   } else if constexpr (KIND == P2_LAPLACE_DIAG || KIND == P2_DIVKGRAD_DIAG) {
     constexpr bool HASK = KIND == P2_DIVKGRAD_DIAG;
     T kv[10], d[10];
@@ -924,7 +1003,7 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
     for (int v = 0; v < 10; ++v) kv[v] = HASK ? sk[li[v]] : T(1);
     p2_diag<T, HASK>(kv, cptr(g->Gp), cptr(g->Gs), d);
 #pragma unroll
-    for (int v = 0; v < 10; ++v) atomicAdd(&sy[0][li[v]], double(d[v]));
+    for (int v = 0; v < 10; ++v) out[v] = d[v];
   } else {
     constexpr bool HASK = KIND != P2_LAPLACE;
     T u[10], kv[10], y[10];
@@ -935,7 +1014,7 @@ __device__ __forceinline__ void tile_elem(const TileArgs<T> &a, const InstDesc<T
     }
     p2_elem<T, HASK>(u, kv, cptr(g->Gp), cptr(g->Gs), y);
 #pragma unroll
-    for (int v = 0; v < 10; ++v) atomicAdd(&sy[0][li[v]], double(y[v]));
+    for (int v = 0; v < 10; ++v) out[v] = y[v];
   }
 }
 
@@ -953,30 +1032,68 @@ constexpr int node_off(int t, int v, int RY, int OO, int RXP) {
   return lds_slot(o[0], o[1] + RY * o[2], OO, RXP);
 }
 
-// micro-tet of type t in cube c of the box (x fastest), if it exists
+// micro-tet of type t in cube c of the box (x fastest): its local results
+// into out[] and its cube's LDS slot into cbo; false if it does not exist
 template <typename T, int KIND, int MAP, int TX, int TY, int TZ, int t, int R>
-__device__ __forceinline__ void cube_elem(const TileArgs<T> &a, const InstDesc<T> *D, T (*sx)[R], const T *sk,
-                                          double (*sy)[R], int m, int bx0, int by0, int bz0, int c, int tw) {
+__device__ __forceinline__ bool cube_elem(const TileArgs<T> &a, const InstDesc<T> *D, T (*sx)[R], const T *sk,
+                                          T *out, int &cbo, int m, int bx0, int by0, int bz0, int c, int tw) {
   using Cfg = TileCfg<T, KIND, MAP, TX, TY, TZ>;
   constexpr int RY = Cfg::RY, OO = Cfg::OO, RXP = Cfg::RXP;
   const int cx = c % TX, cy = (c / TX) % TY, cz = c / (TX * TY);
-  if (bx0 + by0 + bz0 + cx + cy + cz > D->n - kLim[t]) return;
+  if (c >= Cfg::C || bx0 + by0 + bz0 + cx + cy + cz > D->n - kLim[t]) return false;
   const int cb = cx + RXP * (2 * cy + RY * 2 * cz);
+  cbo = cb;
   int li[10];
 #pragma unroll
   for (int v = 0; v < 10; ++v) li[v] = cb + node_off(t, v, RY, OO, RXP);
-  // stored-matrix modes: the element's 55 entries at me[e * C], e = 0..54
-  GPtr<T> me = gptr(Cfg::STORED ? a.mat + (static_cast<int64_t>(tw) * 6 + t) * kStoredEntries * Cfg::C + c : a.mat);
-  tile_elem<T, KIND, MAP, R, t, Cfg::C>(a, D, sx, sk, sy, li, m, bx0 + cx, by0 + cy, bz0 + cz, me);
+  // stored-matrix modes: the element's 55 entries at entry e * C, e = 0..54
+  MatRef me{};
+  if constexpr (Cfg::STORED) {
+    me.r = __builtin_amdgcn_make_buffer_rsrc(a.mat + (static_cast<int64_t>(tw) * 6 + t) * kStoredEntries * Cfg::C, 0,
+                                             kStoredEntries * Cfg::C * static_cast<int>(sizeof(T)), 0x00020000);
+    me.off = c * static_cast<int>(sizeof(T));
+  }
+  tile_elem<T, KIND, MAP, R, t, Cfg::C>(a, D, sx, sk, out, li, m, bx0 + cx, by0 + cy, bz0 + cz, me);
+  return true;
 }
 
-// every cube of the box, micro-tet type t; lane l takes cubes l, l + 64, ...
+// add a micro-tet's local results (cube_elem) into the LDS accumulator
 template <typename T, int KIND, int MAP, int TX, int TY, int TZ, int t, int R>
-__device__ __forceinline__ void type_loop(const TileArgs<T> &a, const InstDesc<T> *D, T (*sx)[R], const T *sk,
-                                          double (*sy)[R], int m, int bx0, int by0, int bz0, int lane, int tw) {
-  constexpr int C = TX * TY * TZ;
-  for (int c = lane; c < C; c += 64)
-    cube_elem<T, KIND, MAP, TX, TY, TZ, t, R>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tw);
+__device__ __forceinline__ void cube_scatter(double (*sy)[R], int cb, const T *out) {
+  using Cfg = TileCfg<T, KIND, MAP, TX, TY, TZ>;
+  constexpr int RY = Cfg::RY, OO = Cfg::OO, RXP = Cfg::RXP;
+  if constexpr (KIND == N1_CURLCURL) {
+#pragma unroll
+    for (int e = 0; e < 6; ++e) atomicAdd(&sy[0][cb + node_off(t, 4 + e, RY, OO, RXP)], double(out[4 + e]));
+  } else {
+    constexpr int NCO = (KIND == P2V_EPSILON || KIND == P2V_EPSILON_DIAG) ? 3 : 1;
+#pragma unroll
+    for (int c = 0; c < NCO; ++c)
+#pragma unroll
+      for (int v = 0; v < 10; ++v) atomicAdd(&sy[c][cb + node_off(t, v, RY, OO, RXP)], double(out[10 * c + v]));
+  }
+}
+
+// one round of micro-tets of type t for wavefront w: the local results into
+// registers, then NW barrier phases, this wavefront adding its results into
+// the accumulator in phase w.  Each type's results stay inside its own branch
+// (a merge after a switch over the types costs ~50 registers in the vector
+// kinds).  Every wavefront passes NW barriers whatever its type.
+template <typename T, int KIND, int MAP, int TX, int TY, int TZ, int t, int R>
+__device__ __forceinline__ void cube_apply(const TileArgs<T> &a, const InstDesc<T> *D, T (*sx)[R], const T *sk,
+                                           double (*sy)[R], int m, int bx0, int by0, int bz0, int c, int tw, int w) {
+  using Cfg = TileCfg<T, KIND, MAP, TX, TY, TZ>;
+  constexpr int NOUT = Cfg::NC == 3 ? 30 : 10, NW = Cfg::NTH / 64;
+  T out[NOUT];
+  int cb = 0;
+  const bool valid = cube_elem<T, KIND, MAP, TX, TY, TZ, t, R>(a, D, sx, sk, out, cb, m, bx0, by0, bz0, c, tw);
+  if constexpr (!Cfg::STORE) {
+#pragma unroll
+    for (int p = 0; p < NW; ++p) {
+      lds_barrier();
+      if (p == w && valid) cube_scatter<T, KIND, MAP, TX, TY, TZ, t, R>(sy, cb, out);
+    }
+  }
 }
 
 // One workgroup per tile.  Workgroup ids are dispatched round-robin over the
@@ -1093,29 +1210,48 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
   }
   __syncthreads();
 
-  // 2. micro-tets
-  if constexpr (!Cfg::EPS) {
-    // wavefront w applies the types t = w (mod WPG) to every cube
-    constexpr int WPG = Cfg::WPG;
+  // 2. micro-tets, in two rounds.  Scalar kinds: wavefront w applies type w
+  // (6 wavefronts: to cubes lane and lane + 64) or types w and w + 3 (3
+  // wavefronts), so the type is a compile-time constant inside each body (LDS
+  // node offsets become instruction immediates, the type's geometry is loaded
+  // once into scalar registers).  Epsilon: slot e = tid + NTH r -> (type e / C,
+  // cube e % C), with 64 | C the type is wave-uniform.  Each round, every
+  // wavefront first computes its micro-tets' results into registers; then
+  // the wavefronts add them into the accumulator one after another, in
+  // wavefront order, between barriers.  Every point therefore receives its
+  // contributions in the same order on every run: results are reproducible
+  // bit for bit (an LDS atomic of one wavefront touches distinct points in
+  // its lanes, and one wavefront's atomics are applied in program order).
+  {
+    constexpr int NW = NTH / 64, C = Cfg::C;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-    if (0 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 0, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane, tl.w);
-    if (1 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 1, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane, tl.w);
-    if (2 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 2, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane, tl.w);
-    if (3 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 3, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane, tl.w);
-    if (4 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 4, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane, tl.w);
-    if (5 % WPG == w) type_loop<T, KIND, MAP, TX, TY, TZ, 5, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, lane, tl.w);
-  } else {
-    // slot e -> (type e / C, cube e % C); 64 | C makes the type wave-uniform
-    constexpr int C = Cfg::C;
-    for (int e = tid; e < 6 * C; e += NTH) {
-      const int t = __builtin_amdgcn_readfirstlane(e / C), c = e - t * C;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      int t, c;
+      if constexpr (Cfg::EPS) {
+        const int e = tid + NTH * r;
+        t = __builtin_amdgcn_readfirstlane(e / C);
+        c = e - t * C;
+      } else if constexpr (Cfg::WPG == 3) {
+        t = w + 3 * r;
+        c = lane;
+      } else {
+        t = w;
+        c = lane + 64 * r;
+      }
       switch (t) {
-        case 0: cube_elem<T, KIND, MAP, TX, TY, TZ, 0, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w); break;
-        case 1: cube_elem<T, KIND, MAP, TX, TY, TZ, 1, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w); break;
-        case 2: cube_elem<T, KIND, MAP, TX, TY, TZ, 2, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w); break;
-        case 3: cube_elem<T, KIND, MAP, TX, TY, TZ, 3, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w); break;
-        case 4: cube_elem<T, KIND, MAP, TX, TY, TZ, 4, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w); break;
-        default: cube_elem<T, KIND, MAP, TX, TY, TZ, 5, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w); break;
+        case 0: cube_apply<T, KIND, MAP, TX, TY, TZ, 0, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w, w); break;
+        case 1: cube_apply<T, KIND, MAP, TX, TY, TZ, 1, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w, w); break;
+        case 2: cube_apply<T, KIND, MAP, TX, TY, TZ, 2, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w, w); break;
+        case 3: cube_apply<T, KIND, MAP, TX, TY, TZ, 3, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w, w); break;
+        case 4: cube_apply<T, KIND, MAP, TX, TY, TZ, 4, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w, w); break;
+        case 5: cube_apply<T, KIND, MAP, TX, TY, TZ, 5, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w, w); break;
+        default:  // no micro-tets this round (vector kinds, round 1): the phases only
+          if constexpr (!Cfg::STORE) {
+#pragma unroll
+            for (int p = 0; p < NW; ++p) lds_barrier();
+          }
+          break;
       }
     }
   }
@@ -1363,16 +1499,6 @@ __global__ __launch_bounds__(256, 5) void k_seam(const SeamInst<T> *__restrict__
 // the element work, for the loads issued before it (the write-back's stores
 // drain during the next sub-box).
 
-// LDS barrier without a wait on global memory (buffer-to-LDS loads and
-// global stores stay in flight): the fences order LDS accesses only
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-// wait for this wavefront's vector memory operations (vmcnt(0); LDS counter untouched)
-__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
-
 template <typename T, int KIND, int S>
 struct MarchCfg {
   static constexpr int TX = 4, TY = 4, TZS = 4;     // sub-box, micro-cubes
@@ -1492,35 +1618,45 @@ __device__ __forceinline__ void lds_add_f64(uint32_t addr, double v) {
   asm volatile("ds_add_f64 %0, %1 offset:%2" ::"v"(addr), "v"(v), "i"(OFF) : "memory");
 }
 
-// the micro-tets of type t in the current sub-box (lane = cube); sy = LDS byte
-// address of the accumulator
+// the micro-tet of type t in the lane's cube of the current sub-box: local
+// results into y[], the cube's LDS slot into cbo; false if it does not exist
 template <typename T, int KIND, int S, int t>
-__device__ __forceinline__ void march_type(CDesc<T> *D, int m, int bsum, LPtr<T> sx, LPtr<T> sk, uint32_t sy,
-                                           int lane) {
+__device__ __forceinline__ bool march_elem(CDesc<T> *D, int m, int bsum, LPtr<T> sx, LPtr<T> sk, int lane, double *y,
+                                           int &cbo) {
   using C = MarchCfg<T, KIND, S>;
   const int cx = lane % C::TX, cy = (lane / C::TX) % C::TY, cz = lane / (C::TX * C::TY);
-  if (bsum + cx + cy + cz > D->n - kLim[t]) return;
+  if (bsum + cx + cy + cz > D->n - kLim[t]) return false;
   const int cb = cx + C::RXP * (2 * cy + C::RY * 2 * cz);
+  cbo = cb;
   const TypeGeo<T> *g = D->geo + 6 * m + t;
-  T u[10], kv[10], y[10];
+  T u[10], kv[10], yt[10];
 #pragma unroll
   for (int v = 0; v < 10; ++v) {
     const int li = cb + node_off(t, v, C::RY, C::OO, C::RXP);
     u[v] = sx[li];
     kv[v] = C::HASK ? sk[li] : T(1);
   }
-  p2_elem<T, C::HASK>(u, kv, cptr(g->Gp), cptr(g->Gs), y);
+  p2_elem<T, C::HASK>(u, kv, cptr(g->Gp), cptr(g->Gs), yt);
+#pragma unroll
+  for (int v = 0; v < 10; ++v) y[v] = double(yt[v]);
+  return true;
+}
+
+// add a micro-tet's results into the accumulator at LDS byte address sy
+template <typename T, int KIND, int S, int t>
+__device__ __forceinline__ void march_scatter(uint32_t sy, int cb, const double *y) {
+  using C = MarchCfg<T, KIND, S>;
   const uint32_t ab = sy + 8u * static_cast<uint32_t>(cb);
-  lds_add_f64<8 * node_off(t, 0, C::RY, C::OO, C::RXP)>(ab, double(y[0]));
-  lds_add_f64<8 * node_off(t, 1, C::RY, C::OO, C::RXP)>(ab, double(y[1]));
-  lds_add_f64<8 * node_off(t, 2, C::RY, C::OO, C::RXP)>(ab, double(y[2]));
-  lds_add_f64<8 * node_off(t, 3, C::RY, C::OO, C::RXP)>(ab, double(y[3]));
-  lds_add_f64<8 * node_off(t, 4, C::RY, C::OO, C::RXP)>(ab, double(y[4]));
-  lds_add_f64<8 * node_off(t, 5, C::RY, C::OO, C::RXP)>(ab, double(y[5]));
-  lds_add_f64<8 * node_off(t, 6, C::RY, C::OO, C::RXP)>(ab, double(y[6]));
-  lds_add_f64<8 * node_off(t, 7, C::RY, C::OO, C::RXP)>(ab, double(y[7]));
-  lds_add_f64<8 * node_off(t, 8, C::RY, C::OO, C::RXP)>(ab, double(y[8]));
-  lds_add_f64<8 * node_off(t, 9, C::RY, C::OO, C::RXP)>(ab, double(y[9]));
+  lds_add_f64<8 * node_off(t, 0, C::RY, C::OO, C::RXP)>(ab, y[0]);
+  lds_add_f64<8 * node_off(t, 1, C::RY, C::OO, C::RXP)>(ab, y[1]);
+  lds_add_f64<8 * node_off(t, 2, C::RY, C::OO, C::RXP)>(ab, y[2]);
+  lds_add_f64<8 * node_off(t, 3, C::RY, C::OO, C::RXP)>(ab, y[3]);
+  lds_add_f64<8 * node_off(t, 4, C::RY, C::OO, C::RXP)>(ab, y[4]);
+  lds_add_f64<8 * node_off(t, 5, C::RY, C::OO, C::RXP)>(ab, y[5]);
+  lds_add_f64<8 * node_off(t, 6, C::RY, C::OO, C::RXP)>(ab, y[6]);
+  lds_add_f64<8 * node_off(t, 7, C::RY, C::OO, C::RXP)>(ab, y[7]);
+  lds_add_f64<8 * node_off(t, 8, C::RY, C::OO, C::RXP)>(ab, y[8]);
+  lds_add_f64<8 * node_off(t, 9, C::RY, C::OO, C::RXP)>(ab, y[9]);
 }
 
 template <typename T, int KIND, int S>
@@ -1618,15 +1754,38 @@ __global__ __launch_bounds__(192) void k_march(TileArgs<T> a) {
       const LPtr<T> sk = (LPtr<T>)(sbuf[cb] + (C::HASK ? C::RPA : 0));
       const uint32_t syb = static_cast<uint32_t>(reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) double *)sy));
       const int bsum = bx0 + by0 + bz0 + C::TZS * cur.sub;
-      if (w == 0) {
-        march_type<T, KIND, S, 0>(D, m, bsum, sx, sk, syb, lane);
-        march_type<T, KIND, S, 3>(D, m, bsum, sx, sk, syb, lane);
-      } else if (w == 1) {
-        march_type<T, KIND, S, 1>(D, m, bsum, sx, sk, syb, lane);
-        march_type<T, KIND, S, 4>(D, m, bsum, sx, sk, syb, lane);
-      } else {
-        march_type<T, KIND, S, 2>(D, m, bsum, sx, sk, syb, lane);
-        march_type<T, KIND, S, 5>(D, m, bsum, sx, sk, syb, lane);
+      // wavefront w: types w (round 0) and w + 3 (round 1); each round the
+      // wavefronts add their results in wavefront order (reproducible sums,
+      // as in k_tile); the untracked LDS atomics are waited for explicitly
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int t = w + 3 * r;
+        double y[10];
+        int cbe = 0;
+        bool valid = false;
+        switch (t) {
+          case 0: valid = march_elem<T, KIND, S, 0>(D, m, bsum, sx, sk, lane, y, cbe); break;
+          case 1: valid = march_elem<T, KIND, S, 1>(D, m, bsum, sx, sk, lane, y, cbe); break;
+          case 2: valid = march_elem<T, KIND, S, 2>(D, m, bsum, sx, sk, lane, y, cbe); break;
+          case 3: valid = march_elem<T, KIND, S, 3>(D, m, bsum, sx, sk, lane, y, cbe); break;
+          case 4: valid = march_elem<T, KIND, S, 4>(D, m, bsum, sx, sk, lane, y, cbe); break;
+          default: valid = march_elem<T, KIND, S, 5>(D, m, bsum, sx, sk, lane, y, cbe); break;
+        }
+#pragma unroll
+        for (int p = 0; p < C::WPG; ++p) {
+          __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+          lds_barrier();
+          if (p == w && valid) {
+            switch (t) {
+              case 0: march_scatter<T, KIND, S, 0>(syb, cbe, y); break;
+              case 1: march_scatter<T, KIND, S, 1>(syb, cbe, y); break;
+              case 2: march_scatter<T, KIND, S, 2>(syb, cbe, y); break;
+              case 3: march_scatter<T, KIND, S, 3>(syb, cbe, y); break;
+              case 4: march_scatter<T, KIND, S, 4>(syb, cbe, y); break;
+              default: march_scatter<T, KIND, S, 5>(syb, cbe, y); break;
+            }
+          }
+        }
       }
     }
     // the element work's LDS atomics, the next sub-box's loads and the
@@ -1763,14 +1922,29 @@ hipError_t launch_tile_apply(const TileArgs<T> &a, int kind, int map, int cfg, h
     case P2_DIVKGRAD_DIAG: return launch_kind<T, P2_DIVKGRAD_DIAG, 0>(a, cfg, s);
     case P2_DIVKGRAD_GRADK: return launch_kind<T, P2_DIVKGRAD_GRADK, 0>(a, cfg, s);
     case P2V_EPSILON_GRADMU:
-      if (cfg != 0) return hipErrorInvalidValue;
-      return map == 0 ? launch_cfg<T, P2V_EPSILON_GRADMU, 0, 4, 4, 4>(a, s)
-                      : launch_cfg<T, P2V_EPSILON_GRADMU, 1, 4, 4, 4>(a, s);
+      if (cfg == 0)
+        return map == 0 ? launch_cfg<T, P2V_EPSILON_GRADMU, 0, 4, 4, 4>(a, s)
+                        : launch_cfg<T, P2V_EPSILON_GRADMU, 1, 4, 4, 4>(a, s);
+      if (cfg == 1)
+        return map == 0 ? launch_cfg<T, P2V_EPSILON_GRADMU, 0, 8, 4, 2>(a, s)
+                        : launch_cfg<T, P2V_EPSILON_GRADMU, 1, 8, 4, 2>(a, s);
+      return hipErrorInvalidValue;
+    case P2V_EPSILON_DIAG:
+      if (cfg == 0)
+        return map == 0 ? launch_cfg<T, P2V_EPSILON_DIAG, 0, 4, 4, 4>(a, s)
+                        : launch_cfg<T, P2V_EPSILON_DIAG, 1, 4, 4, 4>(a, s);
+      if (cfg == 1)
+        return map == 0 ? launch_cfg<T, P2V_EPSILON_DIAG, 0, 8, 4, 2>(a, s)
+                        : launch_cfg<T, P2V_EPSILON_DIAG, 1, 8, 4, 2>(a, s);
+      return hipErrorInvalidValue;
     case P2V_EPSILON:
-      // the epsilon tiles stage 3 components; only the smallest tile fits LDS twice per CU
-      if (cfg != 0) return hipErrorInvalidValue;
-      return map == 0 ? launch_cfg<T, P2V_EPSILON, 0, 4, 4, 4>(a, s)
-                      : launch_cfg<T, P2V_EPSILON, 1, 4, 4, 4>(a, s);
+      // the epsilon tiles stage 3 components: only the 64-cube boxes (4 x 4 x 4
+      // and 8 x 4 x 2, 45 and 50 KB of LDS in FP64) fit twice per CU
+      if (cfg == 0)
+        return map == 0 ? launch_cfg<T, P2V_EPSILON, 0, 4, 4, 4>(a, s) : launch_cfg<T, P2V_EPSILON, 1, 4, 4, 4>(a, s);
+      if (cfg == 1)
+        return map == 0 ? launch_cfg<T, P2V_EPSILON, 0, 8, 4, 2>(a, s) : launch_cfg<T, P2V_EPSILON, 1, 8, 4, 2>(a, s);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
@@ -1789,10 +1963,15 @@ hipError_t launch_seam_gather(const SeamInst<T> *inst, const int4 *work, int nwo
   hipLaunchKernelGGL((k_seam<T, NC_, PPT_, TX_, TY_, TZ_>), grid, dim3(256), sh, s, inst, work, y, active, flags, \
                      rows_lds, partial)
   if (ncomp == 3 || ppt == 1) {
-    // vector fields and the scalar gradient of a vector operator: cfg 0, one point per thread
-    if (cfg != 0 || ppt != 1) return hipErrorInvalidValue;
-    if (ncomp == 3) TMF_SEAM(3, 1, 4, 4, 4);
-    else TMF_SEAM(1, 1, 4, 4, 4);
+    // vector fields and the scalar gradient of a vector operator: cfg 0 or 1, one point per thread
+    if (cfg > 1 || ppt != 1) return hipErrorInvalidValue;
+    if (cfg == 0) {
+      if (ncomp == 3) TMF_SEAM(3, 1, 4, 4, 4);
+      else TMF_SEAM(1, 1, 4, 4, 4);
+    } else {
+      if (ncomp == 3) TMF_SEAM(3, 1, 8, 4, 2);
+      else TMF_SEAM(1, 1, 8, 4, 2);
+    }
     return hipGetLastError();
   }
   if (ppt != kSeamPointsPerThread) return hipErrorInvalidValue;

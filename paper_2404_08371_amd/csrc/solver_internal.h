@@ -16,11 +16,13 @@ struct ChunkDesc {
   int inst;
 };
 
-// per-instance CG state (device arrays of `count` entries)
+// per-instance CG state (device arrays of `count` entries; rr holds two
+// slots of `count`, used alternately by consecutive inner iterations)
 struct CgScalars {
   double *rnorm, *bnorm, *rr, *rr0, *alpha, *beta;
   int *it;
   uint8_t *oact, *iact;  // outer / inner activity
+  int count;
 };
 
 struct BlasCtx {
@@ -29,18 +31,24 @@ struct BlasCtx {
   const int *first;      // count + 1 chunk offsets per instance
   int count;
   const uint8_t *owner;  // NULL when every slot is the only copy of its DoF
-  const float *dinv;     // Jacobi preconditioner 1 / diag(A) (0 on Dirichlet rows), or NULL for none
+  const void *dinv;      // Jacobi preconditioner 1 / diag(A) (0 on Dirichlet rows) in the inner type, or NULL
   CgScalars sc;
 };
 
 hipError_t blas_residual(const BlasCtx &c, const double *b, const double *Ax, double *r, double *prr, double *pbb,
                          double tol, hipStream_t s);
-hipError_t blas_start_inner(const BlasCtx &c, const double *r64, float *r32, float *p, float *d, double *part,
-                            hipStream_t s);
-hipError_t blas_cg_step_after_apply(const BlasCtx &c, float *d, float *r, float *p, const float *q, double *part,
-                                    double rtol2, int maxit, hipStream_t s);
-hipError_t blas_update_x(const BlasCtx &c, double *x, const float *d, hipStream_t s);
-// dinv = 1 / d where d > 0, else 0 (FP64 diagonal in, FP32 out)
-hipError_t blas_inverse_diagonal(const BlasCtx &c, const double *d, float *dinv, hipStream_t s);
+// V = float (FP32 inner iteration) or double (FP64 inner iteration)
+template <typename V>
+hipError_t blas_start_inner(const BlasCtx &c, const double *r64, V *r, V *p, V *d, double *part, hipStream_t s);
+// the inner iteration after q = A p: p.q, alpha and the update, beta and the
+// new direction; ppq and prz hold the per-chunk partials, par the slot parity
+template <typename V>
+hipError_t blas_cg_step_after_apply(const BlasCtx &c, V *d, V *r, V *p, const V *q, double *ppq, double *prz,
+                                    double rtol2, int maxit, int par, hipStream_t s);
+template <typename V>
+hipError_t blas_update_x(const BlasCtx &c, double *x, const V *d, hipStream_t s);
+// dinv = 1 / d where d > 0, else 0 (FP64 diagonal in)
+template <typename V>
+hipError_t blas_inverse_diagonal(const BlasCtx &c, const double *d, V *dinv, hipStream_t s);
 
 }  // namespace tmf

@@ -98,7 +98,11 @@ enum KernelMode {
   P2_DIVKGRAD_STORE = 20,
   P2_STORED_APPLY = 21,
   // P2 div(k grad) with the weights from a quadrature rule (under-integration)
-  P2_DIVKGRAD_Q = 22
+  P2_DIVKGRAD_Q = 22,
+  // diag(A) of the P1 kinds and of the epsilon operator
+  P1_LAPLACE_DIAG = 23,
+  P1_DIVKGRAD_DIAG = 24,
+  P2V_EPSILON_DIAG = 25
 };
 // entries of a stored symmetric 10 x 10 local matrix (upper triangle, row-major)
 constexpr int kStoredEntries = 55;

@@ -141,13 +141,15 @@ class Operator:
         return out
 
     def diagonal(self, coeff=None, out=None):
-        """diag(A(coeff)) in the macro-local layout, every copy holding the total (scalar P2 kinds)."""
+        """diag(A(coeff)) in the macro-local layout (component-major for the epsilon operator),
+        every copy holding the total (P1, exact scalar P2 and epsilon kinds)."""
         pk = self._vec(coeff, "coeff", 1) if self.has_coeff else None
         if not self.has_coeff and coeff is not None:
             raise ValueError("this operator takes no coefficient")
         if out is None:
-            out = torch.empty(self.n_local, dtype=self.dtype, device=coeff.device if coeff is not None else "cuda")
-        pd = self._vec(out, "out", 1)
+            out = torch.empty(self.ncomp * self.n_local, dtype=self.dtype,
+                              device=coeff.device if coeff is not None else "cuda")
+        pd = self._vec(out, "out", self.ncomp)
         with torch.cuda.device(out.device):
             check(lib().tmf_diagonal(self._h, pk, pd, _stream_handle(out.device)))
         return out
@@ -166,6 +168,20 @@ class Operator:
         with torch.cuda.device(x.device):
             check(lib().tmf_apply_stored(self._h, px, self._vec(out, "out", 1), _stream_handle(x.device)))
         return out
+
+    def tune(self, x, coeff=None, y=None, reps=5, cache=None):
+        """Choose the tile shape by timing (tmf_op_tune); with `cache` (a JSON path) a result stored
+        for this operator and device is reused and new results are added.  Returns (cfg, ms)."""
+        px = self._vec(x, "x", self.ncomp)
+        pk = self._vec(coeff, "coeff", self.coeff_comps) if self.has_coeff else None
+        if y is None:
+            y = torch.empty_like(x)
+        cfg, ms = ctypes.c_int(), ctypes.c_float()
+        with torch.cuda.device(x.device):
+            check(lib().tmf_op_tune(self._h, pk, px, self._vec(y, "y", self.ncomp), _stream_handle(x.device),
+                                    int(reps), cache.encode() if cache else None, ctypes.byref(cfg),
+                                    ctypes.byref(ms)))
+        return cfg.value, ms.value
 
     def interface_sum_(self, v):
         """In place: every copy of a shared DoF gets the sum over its copies."""

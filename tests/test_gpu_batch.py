@@ -62,15 +62,22 @@ def test_batch_equals_single_applies():
     assert 0 <= cfg < 7 and ms > 0
 
 
-@pytest.mark.parametrize("use_graph,precond", [(True, T.PRECOND_JACOBI), (False, T.PRECOND_JACOBI),
-                                               (True, T.PRECOND_NONE)])
-def test_iterative_refinement_reaches_fp64_residual(use_graph, precond):
-    print("ir case graph", use_graph, "precond", precond, flush=True)
+@pytest.mark.parametrize("use_graph,precond,inner", [(True, T.PRECOND_JACOBI, T.F32), (False, T.PRECOND_JACOBI, T.F32),
+                                                     (True, T.PRECOND_NONE, T.F32), (True, T.PRECOND_JACOBI, T.F64),
+                                                     (False, T.PRECOND_NONE, T.F64)])
+def test_iterative_refinement_reaches_fp64_residual(use_graph, precond, inner):
+    """Mixed precision (FP32 inner CG) and plain FP64 CG (the FP64 batch as the inner one, inner
+    tolerance below the outer one): FP64 residual <= 1e-10, re-evaluated by the oracle."""
+    print("ir case graph", use_graph, "precond", precond, "inner", inner, flush=True)
     levels = [2, 3, 4, 3, 2, 4]
     inst = make_instances(levels)
     ops64 = [T.Operator(m, T.P2_DIVKGRAD, T.F64) for m, _, _ in inst]
-    ops32 = [T.Operator(m, T.P2_DIVKGRAD, T.F32) for m, _, _ in inst]
-    b64, b32 = T.Batch(ops64), T.Batch(ops32)
+    b64 = T.Batch(ops64)
+    if inner == T.F32:
+        ops32 = [T.Operator(m, T.P2_DIVKGRAD, T.F32) for m, _, _ in inst]
+        b32 = T.Batch(ops32)
+    else:
+        b32 = b64
     ks = [torch.tensor(k, device="cuda") for _, _, k in inst]
     # b = A x* with x* ~ U[-1,1) on interior DoFs (FP64 apply of the library)
     xstar = []
@@ -80,10 +87,13 @@ def test_iterative_refinement_reaches_fp64_residual(use_graph, precond):
     K64 = b64.concat(ks)
     B = b64.apply(b64.concat(xstar), K64)
     X = torch.zeros_like(B)
-    solver = T.IRSolver(b64, b32, tol=1e-10, use_graph=use_graph, graph_iters=8, precond=precond)
-    stats, rel = solver.solve(B, X, K64, K64.float())
+    solver = T.IRSolver(b64, b32, tol=1e-10, use_graph=use_graph, graph_iters=8, precond=precond,
+                        inner_rtol=1e-4 if inner == T.F32 else 1e-11)
+    stats, rel = solver.solve(B, X, K64, K64.float() if inner == T.F32 else K64)
     print("stats", stats, "relres", rel.max())
     assert stats["converged"] and rel.max() <= 1e-10
+    if inner == T.F64:
+        assert stats["outer"] <= 2
     Bn = B.cpu().numpy()
     Xn = X.cpu().numpy()
     v, t = W.meshes.ref_tet()
@@ -98,3 +108,11 @@ def test_iterative_refinement_reaches_fp64_residual(use_graph, precond):
         err = np.linalg.norm(xi - xref) / np.linalg.norm(xref)
         print("instance", i, "level", lvl, "|x-xref|/|xref|", err)
         assert err <= 1e-7
+
+
+def test_solver_options_are_checked():
+    """graph_iters must be even (consecutive inner iterations alternate two slots of r.z)."""
+    inst = make_instances([2, 3])
+    b64 = T.Batch([T.Operator(m, T.P2_DIVKGRAD, T.F64) for m, _, _ in inst])
+    with pytest.raises(T.TetmfError):
+        T.IRSolver(b64, b64, graph_iters=7)

@@ -82,9 +82,48 @@ def test_batch_diagonal_equals_single():
 
 
 def test_diagonal_refused_for_other_kinds():
-    v, t = W.meshes.ref_tet()
+    v, t = W.meshes.kuhn_cube()
     m = T.Mesh(v, t, 2)
-    op = T.Operator(m, T.P1_LAPLACE, T.F64)
+    op = T.Operator(m, T.N1_CURLCURL, T.F64)
     d = torch.empty(op.n_local, dtype=torch.float64, device="cuda")
-    st = T.lib().tmf_diagonal(op.handle, None, ctypes.c_void_p(d.data_ptr()), None)
+    k = torch.ones(2 * op.n_local, dtype=torch.float64, device="cuda")
+    st = T.lib().tmf_diagonal(op.handle, ctypes.c_void_p(k.data_ptr()), ctypes.c_void_p(d.data_ptr()), None)
     assert st == -4  # TMF_EUNSUPPORTED
+
+
+P1_AND_EPS = [("ref", 5, O.P1_LAPLACE), ("cube", 4, O.P1_LAPLACE), ("ref", 6, O.P1_DIVKGRAD), ("cube", 3, O.P1_DIVKGRAD),
+              ("flatshell", 2, O.P1_DIVKGRAD), ("cube", 2, O.P2V_EPSILON), ("flatshell", 3, O.P2V_EPSILON),
+              ("shell", 1, O.P2V_EPSILON), ("shell", 3, O.P2V_EPSILON)]
+
+
+@pytest.mark.parametrize("mesh,level,kind", P1_AND_EPS)
+@pytest.mark.parametrize("bc", [O.BC_DIRICHLET_ZERO, O.BC_NONE])
+@pytest.mark.parametrize("prec", [T.F64, T.F32])
+def test_p1_and_epsilon_diagonal_match_oracle(mesh, level, kind, bc, prec):
+    """diag(D A D) of the P1 kinds (vertex-centric) and of the epsilon operator (per component;
+    affine and radially blended maps) against the oracle."""
+    from test_gpu_parity import lib_problem
+    print("diag case", mesh, level, kind, bc, prec, flush=True)
+    m, op = lib_problem(mesh, level, kind, bc, prec)
+    info = m.dof_info(op.space, owner=False, boundary=False)
+    dt = torch.float64 if prec == T.F64 else torch.float32
+    k = coefficient(kind, info["keys"], info["xyz"], 7)
+    kt = torch.tensor(k, dtype=dt, device="cuda") if k is not None else None
+    out = torch.full((op.ncomp * op.n_local,), float("nan"), dtype=dt, device="cuda")
+    d = op.diagonal(kt, out=out).double().cpu().numpy()
+    assert not np.isnan(d).any()
+    pr = oracle_problem(mesh, level, kind, bc)
+    ref = pr.diagonal(coefficient(kind, pr.keys, pr.xyz, 7))
+    e2, ei = rel_err(d, ref)
+    assert ei <= (1e-12 if prec == T.F64 else 1e-5), (e2, ei)
+
+
+def test_epsilon_diagonal_second_tile_shape():
+    from test_gpu_parity import lib_problem
+    m, op = lib_problem("shell", 2, O.P2V_EPSILON, O.BC_DIRICHLET_ZERO, T.F64)
+    info = m.dof_info(2, owner=False, boundary=False)
+    kt = torch.tensor(coefficient(O.P2V_EPSILON, info["keys"], info["xyz"], 7), device="cuda")
+    d0 = op.diagonal(kt)
+    T.check(T.lib().tmf_op_set_tile(op.handle, 1))
+    d1 = op.diagonal(kt)
+    assert (d0 - d1).abs().max().item() <= 1e-13 * d0.abs().max().item()
