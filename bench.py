@@ -206,6 +206,35 @@ def time_apply(op, x, k, y, steps, warmup, hip, torch, fn=None, stats=None):
     return wall, kernel_mean_ms(hip, evs, stats)
 
 
+def graph_rate(op, x, k, y, torch, per_graph=50, replays=5):
+    """`per_graph` applies captured into one HIP graph (torch's graph capture on a side stream)
+    and replayed `replays` times: (us per apply, whether the replayed result equals an eager
+    apply bit for bit).  Launch overhead is paid once per replay instead of once per apply."""
+    ref = torch.empty_like(y)
+    op.apply(x, k, out=ref)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        op.apply(x, k, out=y)  # anything the apply sets up lazily, outside the capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(per_graph):
+            op.apply(x, k, out=y)
+    y.zero_()
+    g.replay()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(y, ref))
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        g.replay()
+    torch.cuda.synchronize()
+    us = (time.perf_counter() - t0) * 1e6 / (replays * per_graph)
+    del g
+    return us, same
+
+
 def n_elements(mesh_nt, level):
     n = 2 ** level
     return mesh_nt * n ** 3
@@ -468,6 +497,10 @@ def main():
     del scratch
     kstats["cold_kernel_ms_median"] = round(float(np.median(cold_k)), 5)
     kstats["cold_step_ms_median"] = round(float(np.median(cold_s)), 5)
+    # the same step replayed from a HIP graph of 100 applies (launch overhead amortised)
+    gus, gsame = graph_rate(op, x, k, y, torch, per_graph=100)
+    kstats["graph_step_ms"] = round(gus * 1e-3, 5)
+    kstats["graph_step_equals_eager"] = gsame
     nel = n_elements(6, 6)
     flops = nel * FLOPS["p2_divkgrad"]
     bytes_alg = 3 * op.n_local * 8
@@ -516,7 +549,7 @@ def main():
             return sel is None or name in sel
 
         def form(name, mesh, op, fam, seed, flops_launch, bytes_launch, peak_flops, steps, adjoint=False,
-                 dofs=None):
+                 dofs=None, graph=False):
             if not want(name):
                 return
             xx, kk = device_inputs(mesh, op, seed, torch, fam)
@@ -548,6 +581,12 @@ def main():
                  "ms_per_apply": round(w, 5), "kernel_ms": round(kms, 5),
                  "hbm_frac": round(bytes_launch / (kms * 1e-3) / PEAK_HBM, 4),
                  "alu_frac": round(flops_launch / (kms * 1e-3) / peak_flops, 4)}
+            if graph:
+                gus, same = graph_rate(op, xx, kk, yy, torch)
+                r["us_per_launch"] = round(w * 1e3, 2)
+                r["graph_us_per_apply"] = round(gus, 2)
+                r["graph_mdofs"] = round(nd / (gus * 1e-6) / 1e6, 2)
+                r["graph_equals_eager"] = same
             forms[name] = r
             log(name, r)
             del xx, kk, yy
@@ -557,7 +596,7 @@ def main():
             m1 = T.Mesh(vr, tr, lvl)
             o1 = T.Operator(m1, T.P1_LAPLACE, T.F64)
             form("p1_laplace_fp64_reftet_l%d" % lvl, m1, o1, "p1", 1, o1.n_local * FLOPS["p1_laplace"],
-                 16 * o1.n_local, PEAK_FP64, args.form_steps)
+                 16 * o1.n_local, PEAK_FP64, args.form_steps, graph=lvl == 4)
         for lvl in (7, 9):
             m1 = T.Mesh(vr, tr, lvl)
             o1 = T.Operator(m1, T.P1_DIVKGRAD, T.F64)

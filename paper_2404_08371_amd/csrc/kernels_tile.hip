@@ -749,6 +749,27 @@ __device__ __forceinline__ void lds_barrier() {
 // wait for this wavefront's vector memory operations (vmcnt(0); LDS counter untouched)
 __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// Buffer loads and stores over one macro block (or one partial-sum block):
+// the hardware range check turns an offset past the block into a load of 0
+// or a dropped store.
+constexpr int kFarOff = 0x7fffff00;  // byte offset past any block (blocks are < 2^31 bytes)
+constexpr int kStoreNonTemporal = 2;  // cache policy bit NT: outputs not read again by the kernel
+typedef unsigned int U32x2 __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, int off) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <typename T, int AUX>
+__device__ __forceinline__ void buf_st(T v, __amdgpu_buffer_rsrc_t r, int off) {
+  if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, v), r, off, 0, AUX);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, AUX);
+}
+
 template <typename T, int KIND, int MAP, int TX, int TY, int TZ>
 struct TileCfg {
   static constexpr int RX = 2 * TX + 1, RY = 2 * TY + 1, RZ = 2 * TZ + 1;
@@ -1129,66 +1150,85 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
   const uint32_t bnd = D->dirichlet ? *cptr(D->bnd + m) : 0u;
   const int64_t base = D->off + static_cast<int64_t>(m) * D->L;
 
-  // 0. the box's lattice rows (qj, qk): start offset in the macro block, and
-  // packed facts shared by the row's points -- (N - qj - qk) << 8, bit 2/3
-  // qj/qk = 0, bit 4 the row is owned by this box in y and z (write-back)
-  __shared__ int srb[RY * Cfg::RZ];
-  __shared__ int sri[RY * Cfg::RZ];
+  // 0. the box's lattice rows (qj, qk): {offset in the macro block of the
+  // row's first box point (qi = 2 bx0), bits}: bits 0 .. RX-1 mark the box
+  // points whose x is staged (inside the macro and not a Dirichlet DoF), bits
+  // 17 .. 21 hold the last box point inside the macro (khi), bit 22 is set for
+  // a row outside the macro and bit 23 for a row this box owns in y and z
+  // (write-back).  A point's Dirichlet test by its face pattern is folded into
+  // the row: within a row only the two end points can differ from the rest.
+  static_assert(RX <= 17, "the row masks hold at most 17 points");
+  __shared__ int2 srow[RY * Cfg::RZ];
   for (int row = tid; row < RY * Cfg::RZ; row += NTH) {
     const int ry = row % RY, rz = row / RY;
     const int qj = 2 * by0 + ry, qk = 2 * bz0 + rz;
-    const int lim = N - qj - qk;
-    srb[row] = lim >= 0 ? row_base(qj, qk, N) : 0;
+    const int lim = N - qj - qk, L = lim - 2 * bx0;
+    const bool empty = L < 0;
+    const int khi = empty ? 0 : min(L, 2 * TX);
+    const bool limin = !empty && L <= 2 * TX;
+    const int rowzp = ((qj == 0) << 2) | ((qk == 0) << 3);
+    uint32_t xmask = empty ? 0u : (2u << khi) - 1u;
+    if (!empty) {
+      if ((bnd >> rowzp) & 1u) xmask = 0u;
+      if (bx0 == 0 && ((bnd >> (rowzp | 2 | (lim == 0 ? 1 : 0))) & 1u)) xmask &= ~1u;
+      if (limin && ((bnd >> (rowzp | 1 | (lim == 0 ? 2 : 0))) & 1u)) xmask &= ~(1u << khi);
+    }
     const bool ey = (ry & 1) || ((ry > 0 || by0 == 0) && ry < 2 * TY);
     const bool ez = (rz & 1) || ((rz > 0 || bz0 == 0) && rz < 2 * TZ);
-    sri[row] = (lim << 8) | ((qj == 0) << 2) | ((qk == 0) << 3) | ((ey && ez) << 4);
+    srow[row] = make_int2(empty ? 0 : row_base(qj, qk, N) + 2 * bx0,
+                          static_cast<int>(xmask | (uint32_t(khi) << 17) | (uint32_t(empty) << 22) |
+                                           (uint32_t(ey && ez) << 23)));
   }
   __syncthreads();
-  const T *xb[NCI];
-  T *yb[NC];
-#pragma unroll
-  for (int c = 0; c < NCI; ++c) xb[c] = (c < Cfg::NCX ? a.x + c * nl : a.x2 + (c - Cfg::NCX) * nl) + base;
-#pragma unroll
-  for (int c = 0; c < NC; ++c) yb[c] = a.y + base + c * nl;
-  const T *kb = HASK ? a.k + base : nullptr;
 
-  // 1. stage the box: x with Dirichlet DoFs zeroed, and the coefficient.  The
-  // loop is unrolled over a thread's points so that all its loads are in
-  // flight together (one memory latency per tile instead of one per point).
+  // 1. stage the box: x with Dirichlet DoFs zeroed, and the coefficient.
+  // Buffer loads over the macro block: a point outside the macro (or a
+  // Dirichlet DoF of x) gets an offset past the block and loads 0, so there
+  // are no branches and all of a thread's loads are in flight together (one
+  // memory latency per tile instead of one per point).
+  const int nbytes = D->L * static_cast<int>(sizeof(T));
+  __amdgpu_buffer_rsrc_t rsx[NCI], rsk[Cfg::NK];
+#pragma unroll
+  for (int c = 0; c < NCI; ++c)
+    rsx[c] = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<T *>((c < Cfg::NCX ? a.x + c * nl : a.x2 + (c - Cfg::NCX) * nl) + base), 0, nbytes, 0x00020000);
+#pragma unroll
+  for (int c = 0; c < Cfg::NK; ++c)
+    rsk[c] = __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(HASK ? a.k + c * nl + base : a.x + base), 0, nbytes,
+                                               0x00020000);
+  // N1: the per-slot orientation signs (bytes) over the same block
+  const __amdgpu_buffer_rsrc_t rss = __builtin_amdgcn_make_buffer_rsrc(
+      Cfg::N1 ? const_cast<int8_t *>(D->sign + base) : nullptr, 0, Cfg::N1 ? D->L : 0, 0x00020000);
   constexpr int PF = (R + NTH - 1) / NTH, NK = Cfg::NK;
   T xv[PF][NCI], kv[PF][NK];
   int sgv[PF];
 #pragma unroll
   for (int p = 0; p < PF; ++p) {
     const int r = tid + p * NTH;
+    const bool in = r < R;
+    const int rc = in ? r : 0;
+    const int row = rc / RX, rx = rc - row * RX;
+    const int2 rw = srow[row];
+    const uint32_t bits = static_cast<uint32_t>(rw.y);
+    const bool kin = in && !((bits >> 22) & 1u) && rx <= static_cast<int>((bits >> 17) & 31u);
+    const bool xin = in && ((bits >> rx) & 1u);
+    const int off = rw.x + rx;
+#pragma unroll
+    for (int c = 0; c < NCI; ++c)
+      xv[p][c] = (Cfg::DIAG || Cfg::STORE) ? T(0) : buf_ld<T>(rsx[c], xin ? off * static_cast<int>(sizeof(T)) : kFarOff);
     sgv[p] = 0;
+    if constexpr (Cfg::N1) {
+      // x in the lattice orientation; alpha and beta live at the vertex points
+      sgv[p] = static_cast<int8_t>(__builtin_amdgcn_raw_buffer_load_b8(rss, kin ? off : kFarOff, 0, 0));
+      xv[p][0] *= T(sgv[p]);
+      const int ry = row % RY, rz = row / RY;
+      const bool vert = kin && !(rx & 1) && !(ry & 1) && !(rz & 1);
 #pragma unroll
-    for (int c = 0; c < NK; ++c) kv[p][c] = T(0);
+      for (int c = 0; c < NK; ++c) kv[p][c] = buf_ld<T>(rsk[c], vert ? off * static_cast<int>(sizeof(T)) : kFarOff);
+    } else {
 #pragma unroll
-    for (int c = 0; c < NCI; ++c) xv[p][c] = T(0);
-    if (r < R) {
-      const int row = r / RX, rx = r - row * RX;
-      const int info = sri[row], lim = info >> 8, qi = 2 * bx0 + rx;
-      if (qi <= lim) {
-        const int off = srb[row] + qi;
-        const int zp = (qi == lim) | ((qi == 0) << 1) | (info & 12);
-        if (!Cfg::DIAG && !Cfg::STORE && !((bnd >> zp) & 1u)) {
-#pragma unroll
-          for (int c = 0; c < NCI; ++c) xv[p][c] = xb[c][off];
-        }
-        if constexpr (Cfg::N1) {
-          // x in the lattice orientation; alpha and beta live at the vertex points
-          sgv[p] = gptr(D->sign)[base + off];
-          xv[p][0] *= T(sgv[p]);
-          const int ry = row % RY, rz = row / RY;
-          if (!(rx & 1) && !(ry & 1) && !(rz & 1)) {
-            kv[p][0] = kb[off];
-            kv[p][1] = kb[nl + off];
-          }
-        } else if (HASK) {
-          kv[p][0] = kb[off];
-        }
-      }
+      for (int c = 0; c < NK; ++c)
+        kv[p][c] = HASK ? buf_ld<T>(rsk[c], kin ? off * static_cast<int>(sizeof(T)) : kFarOff) : T(0);
     }
   }
 #pragma unroll
@@ -1258,29 +1298,38 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
   if constexpr (Cfg::STORE) return;  // the matrices are the output
   __syncthreads();
 
-  // 3. write back: points of this box alone go to y (Dirichlet DoFs as 0),
-  // points of shared box faces to this tile's partials [component][box point]
-  GPtr<T> pt = gptr(a.partial ? a.partial : D->partial) + static_cast<int64_t>(tl.w) * NC * R;
-  for (int r = tid; r < R; r += NTH) {
-    const int row = r / RX, rx = r - row * RX;
-    const int info = sri[row], lim = info >> 8, qi = 2 * bx0 + rx;
-    if (qi > lim) continue;
-    const int zp = (qi == lim) | ((qi == 0) << 1) | (info & 12);
-    const bool excl = ((info >> 4) & 1) && ((rx & 1) || ((rx > 0 || bx0 == 0) && rx < 2 * TX));
-    const int sl = lds_slot(rx, row, OO, RXP);
-    // N1: back to the global orientation (partials too, so that the gather
-    // adds values of one orientation)
-    const T osg = Cfg::N1 ? T(ssg[sl]) : T(1);
-    if (excl) {
-      const bool dir = !Cfg::GRAD && ((bnd >> zp) & 1u);
-      const int off = srb[row] + qi;
+  // 3. write back: points of this box alone go to y (Dirichlet DoFs as 0,
+  // non-temporal), points of shared box faces to this tile's partials
+  // [component][box point].  Both stores are issued for every point, one of
+  // them (and both for a point outside the macro) at an offset past its
+  // buffer, which drops it: no branches around the stores.
+  {
+    __amdgpu_buffer_rsrc_t rsy[NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) __builtin_nontemporal_store(dir ? T(0) : osg * T(sy[c][sl]), &yb[c][off]);
-    } else {
-      // plain stores: the gather kernel reads these next (measured faster
-      // than non-temporal ones, and than a compact surface-only layout)
+    for (int c = 0; c < NC; ++c)
+      rsy[c] = __builtin_amdgcn_make_buffer_rsrc(a.y + base + c * nl, 0, nbytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsp = __builtin_amdgcn_make_buffer_rsrc(
+        (a.partial ? a.partial : D->partial) + static_cast<int64_t>(tl.w) * NC * R, 0,
+        NC * R * static_cast<int>(sizeof(T)), 0x00020000);
+    for (int r = tid; r < R; r += NTH) {
+      const int row = r / RX, rx = r - row * RX;
+      const int2 rw = srow[row];
+      const uint32_t bits = static_cast<uint32_t>(rw.y);
+      const bool valid = !((bits >> 22) & 1u) && rx <= static_cast<int>((bits >> 17) & 31u);
+      const bool excl = ((bits >> 23) & 1u) && ((rx & 1) || ((rx > 0 || bx0 == 0) && rx < 2 * TX));
+      // a point inside the macro whose x bit is clear is a Dirichlet DoF
+      const bool dir = !Cfg::GRAD && !((bits >> rx) & 1u);
+      const int sl = lds_slot(rx, row, OO, RXP);
+      // N1: back to the global orientation (partials too, so that the gather
+      // adds values of one orientation)
+      const T osg = Cfg::N1 ? T(ssg[sl]) : T(1);
+      const int yo = valid && excl ? (rw.x + rx) * static_cast<int>(sizeof(T)) : kFarOff;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) pt[c * R + r] = osg * T(sy[c][sl]);
+      for (int c = 0; c < NC; ++c) {
+        const T v = osg * T(sy[c][sl]);
+        buf_st<T, kStoreNonTemporal>(dir ? T(0) : v, rsy[c], yo);
+        buf_st<T, 0>(v, rsp, valid && !excl ? (c * R + r) * static_cast<int>(sizeof(T)) : kFarOff);
+      }
     }
   }
 }
