@@ -200,26 +200,51 @@ struct Window {
   T c[3], u[2], d[2];
 };
 
+// Whole-wavefront shifts by one lane as DPP moves (wave_shl:1 / wave_shr:1,
+// GFX9 data-parallel controls): a VALU move per dword, where a generic shuffle
+// goes through the LDS crossbar (ds_bpermute) and waits on it.  The lane that
+// has no source (63 for the left shift, 0 for the right) receives 0; those
+// two lanes are halo lanes and produce no output.
+typedef unsigned int U32x2 __attribute__((ext_vector_type(2)));
+constexpr int kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138;
+template <int CTRL>
+__device__ __forceinline__ double wave_shift(double v) {
+  const U32x2 p = __builtin_bit_cast(U32x2, v);
+  U32x2 r;
+  r.x = static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(p.x), CTRL, 0xF, 0xF, true));
+  r.y = static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(p.y), CTRL, 0xF, 0xF, true));
+  return __builtin_bit_cast(double, r);
+}
+template <int CTRL>
+__device__ __forceinline__ float wave_shift(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+// value of lane + 1 / lane - 1
+template <typename T>
+__device__ __forceinline__ T from_next(T v) { return wave_shift<kDppWaveShl1>(v); }
+template <typename T>
+__device__ __forceinline__ T from_prev(T v) { return wave_shift<kDppWaveShr1>(v); }
+
 // the 15-point neighbourhood of each lane's point, in the slot layout of
 // kNbPlane / kNbSlot (in-plane offsets (0,0) (1,0) (-1,0) (0,1) (0,-1) (1,-1)
 // (-1,1)); i + 1 comes from lane + 1, i - 1 from lane - 1
 template <typename T>
 __device__ __forceinline__ void neighbourhood(const Window<T> &w, T P[3][7]) {
   P[1][0] = w.c[1];
-  P[1][1] = __shfl_down(w.c[1], 1, 64);
-  P[1][2] = __shfl_up(w.c[1], 1, 64);
+  P[1][1] = from_next(w.c[1]);
+  P[1][2] = from_prev(w.c[1]);
   P[1][3] = w.c[2];
-  P[1][6] = __shfl_up(w.c[2], 1, 64);
+  P[1][6] = from_prev(w.c[2]);
   P[1][4] = w.c[0];
-  P[1][5] = __shfl_down(w.c[0], 1, 64);
+  P[1][5] = from_next(w.c[0]);
   P[2][0] = w.u[1];
-  P[2][2] = __shfl_up(w.u[1], 1, 64);
+  P[2][2] = from_prev(w.u[1]);
   P[2][4] = w.u[0];
-  P[2][5] = __shfl_down(w.u[0], 1, 64);
+  P[2][5] = from_next(w.u[0]);
   P[0][0] = w.d[0];
-  P[0][1] = __shfl_down(w.d[0], 1, 64);
+  P[0][1] = from_next(w.d[0]);
   P[0][3] = w.d[1];
-  P[0][6] = __shfl_up(w.d[1], 1, 64);
+  P[0][6] = from_prev(w.d[1]);
   // slots no 15-point neighbour uses
   P[2][1] = P[2][3] = P[2][6] = T(0);
   P[0][2] = P[0][4] = P[0][5] = T(0);
@@ -242,7 +267,6 @@ __device__ __forceinline__ double buf_load(double, Rsrc r, int off) {
 __device__ __forceinline__ float buf_load(float, Rsrc r, int off) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
-typedef unsigned int U32x2 __attribute__((ext_vector_type(2)));
 // outputs are written once and not read again by the kernel: non-temporal
 // stores (cache policy bit NT) keep them from evicting input rows from L2
 constexpr int kStoreNT = 2;
