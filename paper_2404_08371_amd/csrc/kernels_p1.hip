@@ -90,37 +90,42 @@ __device__ __forceinline__ void centred(const T P[3][7], T D[3][7]) {
 }
 
 // row p of sum_T kbar_T Gp_T x_T over the existing micro-tets containing p
-// (p is local vertex a of the type-t micro-tet; DX = centred x)
-template <typename T, int t, int a>
+// (p is local vertex a of the type-t micro-tet; DX = centred x).  ALL: every
+// micro-tet around p exists (a wavefront of interior points), no per-tet
+// test.  The factor 1/4 of the vertex mean kbar is applied once to the sum
+// (a power of two: the same result as per term).
+template <typename T, int t, int a, bool ALL>
 __device__ __forceinline__ void p1k_tet(GeoPtr<T> g, const T DX[3][7], const T K[3][7], int z, T &acc) {
   T r = T(0);
 #pragma unroll
   for (int c = 0; c < 4; ++c)
     if (c != a) r += goff(g, t, a, c) * nbval(DX, kVS.v[t][a][c]);
   const int q0 = kVS.v[t][a][0], q1 = kVS.v[t][a][1], q2 = kVS.v[t][a][2], q3 = kVS.v[t][a][3];
-  const T kb = (nbval(K, q0) + nbval(K, q1) + nbval(K, q2) + nbval(K, q3)) * T(0.25);
-  const T c = kb * r;
-  acc += tet_exists<t, a>(z) ? c : T(0);
+  const T ks = (nbval(K, q0) + nbval(K, q1)) + (nbval(K, q2) + nbval(K, q3));
+  if constexpr (ALL)
+    acc += ks * r;
+  else
+    acc += tet_exists<t, a>(z) ? ks * r : T(0);
 }
 
-template <typename T>
+template <typename T, bool ALL>
 __device__ __forceinline__ T p1k_row(GeoPtr<T> g, const T X[3][7], const T K[3][7], int z) {
   T DX[3][7];
   centred(X, DX);
   T acc = T(0);
-  p1k_tet<T, 0, 0>(g, DX, K, z, acc); p1k_tet<T, 0, 1>(g, DX, K, z, acc);
-  p1k_tet<T, 0, 2>(g, DX, K, z, acc); p1k_tet<T, 0, 3>(g, DX, K, z, acc);
-  p1k_tet<T, 1, 0>(g, DX, K, z, acc); p1k_tet<T, 1, 1>(g, DX, K, z, acc);
-  p1k_tet<T, 1, 2>(g, DX, K, z, acc); p1k_tet<T, 1, 3>(g, DX, K, z, acc);
-  p1k_tet<T, 2, 0>(g, DX, K, z, acc); p1k_tet<T, 2, 1>(g, DX, K, z, acc);
-  p1k_tet<T, 2, 2>(g, DX, K, z, acc); p1k_tet<T, 2, 3>(g, DX, K, z, acc);
-  p1k_tet<T, 3, 0>(g, DX, K, z, acc); p1k_tet<T, 3, 1>(g, DX, K, z, acc);
-  p1k_tet<T, 3, 2>(g, DX, K, z, acc); p1k_tet<T, 3, 3>(g, DX, K, z, acc);
-  p1k_tet<T, 4, 0>(g, DX, K, z, acc); p1k_tet<T, 4, 1>(g, DX, K, z, acc);
-  p1k_tet<T, 4, 2>(g, DX, K, z, acc); p1k_tet<T, 4, 3>(g, DX, K, z, acc);
-  p1k_tet<T, 5, 0>(g, DX, K, z, acc); p1k_tet<T, 5, 1>(g, DX, K, z, acc);
-  p1k_tet<T, 5, 2>(g, DX, K, z, acc); p1k_tet<T, 5, 3>(g, DX, K, z, acc);
-  return acc;
+  p1k_tet<T, 0, 0, ALL>(g, DX, K, z, acc); p1k_tet<T, 0, 1, ALL>(g, DX, K, z, acc);
+  p1k_tet<T, 0, 2, ALL>(g, DX, K, z, acc); p1k_tet<T, 0, 3, ALL>(g, DX, K, z, acc);
+  p1k_tet<T, 1, 0, ALL>(g, DX, K, z, acc); p1k_tet<T, 1, 1, ALL>(g, DX, K, z, acc);
+  p1k_tet<T, 1, 2, ALL>(g, DX, K, z, acc); p1k_tet<T, 1, 3, ALL>(g, DX, K, z, acc);
+  p1k_tet<T, 2, 0, ALL>(g, DX, K, z, acc); p1k_tet<T, 2, 1, ALL>(g, DX, K, z, acc);
+  p1k_tet<T, 2, 2, ALL>(g, DX, K, z, acc); p1k_tet<T, 2, 3, ALL>(g, DX, K, z, acc);
+  p1k_tet<T, 3, 0, ALL>(g, DX, K, z, acc); p1k_tet<T, 3, 1, ALL>(g, DX, K, z, acc);
+  p1k_tet<T, 3, 2, ALL>(g, DX, K, z, acc); p1k_tet<T, 3, 3, ALL>(g, DX, K, z, acc);
+  p1k_tet<T, 4, 0, ALL>(g, DX, K, z, acc); p1k_tet<T, 4, 1, ALL>(g, DX, K, z, acc);
+  p1k_tet<T, 4, 2, ALL>(g, DX, K, z, acc); p1k_tet<T, 4, 3, ALL>(g, DX, K, z, acc);
+  p1k_tet<T, 5, 0, ALL>(g, DX, K, z, acc); p1k_tet<T, 5, 1, ALL>(g, DX, K, z, acc);
+  p1k_tet<T, 5, 2, ALL>(g, DX, K, z, acc); p1k_tet<T, 5, 3, ALL>(g, DX, K, z, acc);
+  return acc * T(0.25);
 }
 
 // diagonal entry of row p: sum over the existing micro-tets containing p of
@@ -155,8 +160,8 @@ __device__ __forceinline__ T p1k_diag(GeoPtr<T> g, const T K[3][7], int z) {
 }
 
 // 1/4 (D gy)_T . Gp_T (D x)_T summed over the existing micro-tets containing p
-// (DR, DX centred gy and x)
-template <typename T, int t, int a>
+// (DR, DX centred gy and x; ALL as in p1k_tet)
+template <typename T, int t, int a, bool ALL>
 __device__ __forceinline__ void kgrad_tet(GeoPtr<T> g, const T DR[3][7], const T DX[3][7], int z, T &acc) {
   T bil = T(0);
 #pragma unroll
@@ -166,27 +171,30 @@ __device__ __forceinline__ void kgrad_tet(GeoPtr<T> g, const T DR[3][7], const T
       const int q1 = kVS.v[t][a][c1], q2 = kVS.v[t][a][c2];
       bil -= goff(g, t, c1, c2) * (nbval(DR, q1) - nbval(DR, q2)) * (nbval(DX, q1) - nbval(DX, q2));
     }
-  acc += tet_exists<t, a>(z) ? bil : T(0);
+  if constexpr (ALL)
+    acc += bil;
+  else
+    acc += tet_exists<t, a>(z) ? bil : T(0);
 }
 
-template <typename T>
+template <typename T, bool ALL>
 __device__ __forceinline__ T kgrad_row(GeoPtr<T> g, const T R[3][7], const T X[3][7], int z) {
   T DR[3][7], DX[3][7];
   centred(R, DR);
   centred(X, DX);
   T acc = T(0);
-  kgrad_tet<T, 0, 0>(g, DR, DX, z, acc); kgrad_tet<T, 0, 1>(g, DR, DX, z, acc);
-  kgrad_tet<T, 0, 2>(g, DR, DX, z, acc); kgrad_tet<T, 0, 3>(g, DR, DX, z, acc);
-  kgrad_tet<T, 1, 0>(g, DR, DX, z, acc); kgrad_tet<T, 1, 1>(g, DR, DX, z, acc);
-  kgrad_tet<T, 1, 2>(g, DR, DX, z, acc); kgrad_tet<T, 1, 3>(g, DR, DX, z, acc);
-  kgrad_tet<T, 2, 0>(g, DR, DX, z, acc); kgrad_tet<T, 2, 1>(g, DR, DX, z, acc);
-  kgrad_tet<T, 2, 2>(g, DR, DX, z, acc); kgrad_tet<T, 2, 3>(g, DR, DX, z, acc);
-  kgrad_tet<T, 3, 0>(g, DR, DX, z, acc); kgrad_tet<T, 3, 1>(g, DR, DX, z, acc);
-  kgrad_tet<T, 3, 2>(g, DR, DX, z, acc); kgrad_tet<T, 3, 3>(g, DR, DX, z, acc);
-  kgrad_tet<T, 4, 0>(g, DR, DX, z, acc); kgrad_tet<T, 4, 1>(g, DR, DX, z, acc);
-  kgrad_tet<T, 4, 2>(g, DR, DX, z, acc); kgrad_tet<T, 4, 3>(g, DR, DX, z, acc);
-  kgrad_tet<T, 5, 0>(g, DR, DX, z, acc); kgrad_tet<T, 5, 1>(g, DR, DX, z, acc);
-  kgrad_tet<T, 5, 2>(g, DR, DX, z, acc); kgrad_tet<T, 5, 3>(g, DR, DX, z, acc);
+  kgrad_tet<T, 0, 0, ALL>(g, DR, DX, z, acc); kgrad_tet<T, 0, 1, ALL>(g, DR, DX, z, acc);
+  kgrad_tet<T, 0, 2, ALL>(g, DR, DX, z, acc); kgrad_tet<T, 0, 3, ALL>(g, DR, DX, z, acc);
+  kgrad_tet<T, 1, 0, ALL>(g, DR, DX, z, acc); kgrad_tet<T, 1, 1, ALL>(g, DR, DX, z, acc);
+  kgrad_tet<T, 1, 2, ALL>(g, DR, DX, z, acc); kgrad_tet<T, 1, 3, ALL>(g, DR, DX, z, acc);
+  kgrad_tet<T, 2, 0, ALL>(g, DR, DX, z, acc); kgrad_tet<T, 2, 1, ALL>(g, DR, DX, z, acc);
+  kgrad_tet<T, 2, 2, ALL>(g, DR, DX, z, acc); kgrad_tet<T, 2, 3, ALL>(g, DR, DX, z, acc);
+  kgrad_tet<T, 3, 0, ALL>(g, DR, DX, z, acc); kgrad_tet<T, 3, 1, ALL>(g, DR, DX, z, acc);
+  kgrad_tet<T, 3, 2, ALL>(g, DR, DX, z, acc); kgrad_tet<T, 3, 3, ALL>(g, DR, DX, z, acc);
+  kgrad_tet<T, 4, 0, ALL>(g, DR, DX, z, acc); kgrad_tet<T, 4, 1, ALL>(g, DR, DX, z, acc);
+  kgrad_tet<T, 4, 2, ALL>(g, DR, DX, z, acc); kgrad_tet<T, 4, 3, ALL>(g, DR, DX, z, acc);
+  kgrad_tet<T, 5, 0, ALL>(g, DR, DX, z, acc); kgrad_tet<T, 5, 1, ALL>(g, DR, DX, z, acc);
+  kgrad_tet<T, 5, 2, ALL>(g, DR, DX, z, acc); kgrad_tet<T, 5, 3, ALL>(g, DR, DX, z, acc);
   return acc * T(0.25);
 }
 
@@ -406,7 +414,8 @@ __global__ __launch_bounds__(256) void k_p1_apply(P1Args<T> a, const int4 *__res
     } else if (VARK) {
       T PK[3][7];
       neighbourhood(K, PK);
-      acc = p1k_row(g, PX, PK, z);
+      // wavefront-uniform: all output points interior -> no per-tet tests
+      acc = __ballot(out && z != 0) == 0 ? p1k_row<T, true>(g, PX, PK, z) : p1k_row<T, false>(g, PX, PK, z);
     } else if (__ballot(out && z != 0) == 0) {
       // every output point of the row segment lies inside the macro
 #pragma unroll
@@ -569,9 +578,12 @@ __global__ __launch_bounds__(256) void k_p1_adjoint(P1AdjArgs<T> a, const int4 *
     neighbourhood(X, PX);
     neighbourhood(K, PK);
     const int z = zero_pattern(i, j, k, N);
-    const T gx = ((dm >> z) & 1u) ? T(0) : p1k_row(g, PG, PK, z);
-    const T gk = kgrad_row(g, PG, PX, z);
-    const int off = point_off<T>(out_lane && i <= N - j - k, i, j, k, N);
+    const bool out = out_lane && i <= N - j - k;
+    // (one body for all points: an interior-only copy beside it raised the
+    // kernel from 241 to 384 VGPRs)
+    const T gx = ((dm >> z) & 1u) ? T(0) : p1k_row<T, false>(g, PG, PK, z);
+    const T gk = kgrad_row<T, false>(g, PG, PX, z);
+    const int off = point_off<T>(out, i, j, k, N);
     buf_store(gx, gxr, off);
     buf_store(gk, gkr, off);
     window_slide(G);
