@@ -258,9 +258,14 @@ def kernel_code_hash(sources=KERNEL_SOURCES, csrc=None):
     return h.hexdigest()[:16]
 
 
+# tile-shape indices from this one on are the marching shapes (see the tile-shape table of the library)
+MARCH_CFG0 = 4
+
+
 def traffic_for(kernel_key, tile, field="bytes_per_launch_by_tile"):
-    """HBM bytes per launch of one element-kernel tile shape (or, with field
-    "seam_bytes_per_launch_by_tile", of the seam reduction launched after it), from the committed
+    """HBM bytes per launch of one element-kernel tile shape, keyed "TXxTYxTZ" (a marching column:
+    "march:TXxTYxTZ"), or, with field "seam_bytes_per_launch_by_tile", of the seam reduction
+    launched after it, from the committed
     rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a 1 GiB copy);
     None when the kernel code has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -271,7 +276,7 @@ def traffic_for(kernel_key, tile, field="bytes_per_launch_by_tile"):
     ent = data.get(kernel_key)
     if not ent or kernel_code_hash(tuple(ent.get("sources", ()))) != ent.get("code_sha256_16"):
         return None
-    return ent.get(field, {}).get("x".join(str(v) for v in tile))
+    return ent.get(field, {}).get(tile)
 
 
 def batched_solve(torch, T, W, hip, steps):
@@ -511,8 +516,10 @@ def main():
     else:
         achieved, peak, unit = bytes_alg / (kern * 1e-3) / 1e9, PEAK_HBM / 1e9, "GB/s"
     tile = (tx.value, ty.value, tz.value)
-    traffic = traffic_for("p2_divkgrad_fp64_cube6", tile)
-    seam_traffic = traffic_for("p2_divkgrad_fp64_cube6", tile, "seam_bytes_per_launch_by_tile")
+    # marching shapes (a column of 4 x 4 x 4 sub-boxes) run another kernel than a box of the same size
+    tkey = ("march:" if cfg.value >= MARCH_CFG0 else "") + "x".join(str(v) for v in tile)
+    traffic = traffic_for("p2_divkgrad_fp64_cube6", tkey)
+    seam_traffic = traffic_for("p2_divkgrad_fp64_cube6", tkey, "seam_bytes_per_launch_by_tile")
     value = op.n_unique / (wall * 1e-3) / 1e6
     out = {
         "metric": "operator-apply MDoF/s (FP64 vs FP32-refined, fwd+adjoint) and % HBM roofline",
