@@ -424,13 +424,42 @@ __device__ inline void eps_elem(const T u[3][10], const T mu[10], CPtr<T> grad, 
 // v = s/|xi| - rho xi/|xi|^3.  Since v.xi = 0, DPhi^-1 = (I - xi v^T/a0)/a0
 // and det DPhi = a0^3; J^-1 = JT^-1 DPhi^-1, whose first factor is the
 // micro-tet's (constant) barycentric gradients.
+// 1 / sqrt(v) and 1 / v (v > 0) from the hardware estimates refined by
+// Newton's iteration (reciprocal square root: y <- y (3 - v y^2) / 2;
+// reciprocal: y <- y + y (1 - v y)); each step doubles the correct bits, two
+// steps reach double precision to a few ulp, one step single precision
+template <typename T>
+__device__ __forceinline__ T rsqrt_nr(T v) {
+  if constexpr (sizeof(T) == 8) {
+    T y = __builtin_amdgcn_rsq(v);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) y = y * (T(1.5) - T(0.5) * v * y * y);
+    return y;
+  } else {
+    const T y = __builtin_amdgcn_rsqf(v);
+    return y * (T(1.5) - T(0.5) * v * y * y);
+  }
+}
+template <typename T>
+__device__ __forceinline__ T rcp_nr(T v) {
+  if constexpr (sizeof(T) == 8) {
+    T y = __builtin_amdgcn_rcp(v);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) y = y + y * (T(1) - v * y);
+    return y;
+  } else {
+    const T y = __builtin_amdgcn_rcpf(v);
+    return y + y * (T(1) - v * y);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T shell_map(const T P0[3], CPtr<T> JT, const T s[3], const T xh[3], T xi[3], T v[3]) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) xi[d] = P0[d] + JT[3 * d + 0] * xh[0] + JT[3 * d + 1] * xh[1] + JT[3 * d + 2] * xh[2];
   const T rho = s[0] * xi[0] + s[1] * xi[1] + s[2] * xi[2];
   const T n2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
-  const T inv = T(1) / sqrt(n2);
+  const T inv = rsqrt_nr(n2);
   const T c3i = rho * inv * inv * inv;
 #pragma unroll
   for (int d = 0; d < 3; ++d) v[d] = s[d] * inv - c3i * xi[d];
@@ -483,7 +512,7 @@ __device__ inline void eps_blended_elem(const T u[3][10], const T mu[10], const 
     const T xh[3] = {Q[2], Q[3], Q[4]};
     T xi[3], v[3];
     const T a0 = shell_map(P0, JT, s, xh, xi, v);
-    const T ia0 = T(1) / a0;
+    const T ia0 = rcp_nr(a0);
     T gu[3][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -646,7 +675,7 @@ __device__ inline void eps_blended_gradmu(const T u[3][10], const T gy[3][10], c
     const T xh[3] = {Q[2], Q[3], Q[4]};
     T xi[3], v[3];
     const T a0 = shell_map(P0, JT, s, xh, xi, v);
-    const T ia0 = T(1) / a0;
+    const T ia0 = rcp_nr(a0);
     T gu[3][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -1101,7 +1130,8 @@ __device__ __forceinline__ void cube_scatter(double (*sy)[R], int cb, const T *o
 // kinds).  Every wavefront passes NW barriers whatever its type.
 template <typename T, int KIND, int MAP, int TX, int TY, int TZ, int t, int R>
 __device__ __forceinline__ void cube_apply(const TileArgs<T> &a, const InstDesc<T> *D, T (*sx)[R], const T *sk,
-                                           double (*sy)[R], int m, int bx0, int by0, int bz0, int c, int tw, int w) {
+                                           double (*sy)[R], int m, int bx0, int by0, int bz0, int c, int tw, int w,
+                                           bool first) {
   using Cfg = TileCfg<T, KIND, MAP, TX, TY, TZ>;
   constexpr int NOUT = Cfg::NC == 3 ? 30 : 10, NW = Cfg::NTH / 64;
   T out[NOUT];
@@ -1110,7 +1140,9 @@ __device__ __forceinline__ void cube_apply(const TileArgs<T> &a, const InstDesc<
   if constexpr (!Cfg::STORE) {
 #pragma unroll
     for (int p = 0; p < NW; ++p) {
-      lds_barrier();
+      // (the first round's first phase needs no barrier: the staging barrier
+      // came before, and the other wavefronts' work reads only x and k)
+      if (p > 0 || !first) lds_barrier();
       if (p == w && valid) cube_scatter<T, KIND, MAP, TX, TY, TZ, t, R>(sy, cb, out);
     }
   }
@@ -1279,16 +1311,17 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
         c = lane + 64 * r;
       }
       switch (t) {
-        case 0: cube_apply<T, KIND, MAP, TX, TY, TZ, 0, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w, w); break;
-        case 1: cube_apply<T, KIND, MAP, TX, TY, TZ, 1, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w, w); break;
-        case 2: cube_apply<T, KIND, MAP, TX, TY, TZ, 2, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w, w); break;
-        case 3: cube_apply<T, KIND, MAP, TX, TY, TZ, 3, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w, w); break;
-        case 4: cube_apply<T, KIND, MAP, TX, TY, TZ, 4, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w, w); break;
-        case 5: cube_apply<T, KIND, MAP, TX, TY, TZ, 5, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w, w); break;
+        case 0: cube_apply<T, KIND, MAP, TX, TY, TZ, 0, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w, w, r == 0); break;
+        case 1: cube_apply<T, KIND, MAP, TX, TY, TZ, 1, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w, w, r == 0); break;
+        case 2: cube_apply<T, KIND, MAP, TX, TY, TZ, 2, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w, w, r == 0); break;
+        case 3: cube_apply<T, KIND, MAP, TX, TY, TZ, 3, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w, w, r == 0); break;
+        case 4: cube_apply<T, KIND, MAP, TX, TY, TZ, 4, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w, w, r == 0); break;
+        case 5: cube_apply<T, KIND, MAP, TX, TY, TZ, 5, RP>(a, D, sx, sk, sy, m, bx0, by0, bz0, c, tl.w, w, r == 0); break;
         default:  // no micro-tets this round (vector kinds, round 1): the phases only
           if constexpr (!Cfg::STORE) {
 #pragma unroll
-            for (int p = 0; p < NW; ++p) lds_barrier();
+            for (int p = 0; p < NW; ++p)
+              if (p > 0 || r != 0) lds_barrier();
           }
           break;
       }
