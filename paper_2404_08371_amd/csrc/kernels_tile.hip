@@ -1383,6 +1383,9 @@ __device__ __forceinline__ bool is_seam(int qx, int qy, int qz) {
 // Macro m's partial sums form one block of tpm NC R values, below 10^9 bytes
 // at the largest level, so a candidate is addressed by the block's 64-bit base
 // (uniform over a seam work entry) and a 32-bit byte offset.
+// macro-local slot of a packed lattice point qx | qy << 10 | qz << 20
+__device__ __forceinline__ int seam_slot(int pk, int N) { return row_base((pk >> 10) & 1023, pk >> 20, N) + (pk & 1023); }
+
 template <typename T, int NC, int TX, int TY, int TZ>
 __device__ __forceinline__ GPtr<const char> partial_block(const SeamInst<T> &a, const T *ovr, int m) {
   constexpr int R = (2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1);
@@ -1498,7 +1501,6 @@ __global__ __launch_bounds__(256, 5) void k_seam(const SeamInst<T> *__restrict__
       const uint32_t sh = local ? 0u : *cptr(a.shared + m);
       const GPtr<const char> pmw = partial_block<T, NC, TX, TY, TZ>(a, partial, w.y);
       T acc[PPT][NC];
-      int64_t sl[PPT];
       bool wr[PPT], dz[PPT];
 #pragma unroll
       for (int u = 0; u < PPT; ++u) {
@@ -1507,7 +1509,6 @@ __global__ __launch_bounds__(256, 5) void k_seam(const SeamInst<T> *__restrict__
         const int z = zero_pattern(qx, qy, qz, a.N);
         wr[u] = pks[u] >= 0 && !((sh >> z) & 1u);
         dz[u] = (bm >> z) & 1u;
-        sl[u] = static_cast<int64_t>(m) * a.L + row_base(qy, qz, a.N) + qx;
         seam_sum<T, NC, TX, TY, TZ>(a, rs, pmw, qx, qy, qz, acc[u]);
       }
 #pragma unroll
@@ -1515,7 +1516,7 @@ __global__ __launch_bounds__(256, 5) void k_seam(const SeamInst<T> *__restrict__
         if (wr[u])
 #pragma unroll
           for (int c = 0; c < NC; ++c)
-            yi[sl[u] + c * a.n_local] = dz[u] ? T(0) : acc[u][c];
+            yi[static_cast<int64_t>(m) * a.L + seam_slot(pks[u], a.N) + c * a.n_local] = dz[u] ? T(0) : acc[u][c];
       return;
     }
     const int pk = pks[0];
