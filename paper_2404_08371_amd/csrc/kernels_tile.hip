@@ -1189,8 +1189,39 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
   // (write-back).  A point's Dirichlet test by its face pattern is folded into
   // the row: within a row only the two end points can differ from the rest.
   static_assert(RX <= 17, "the row masks hold at most 17 points");
-  __shared__ int2 srow[RY * Cfg::RZ];
-  for (int row = tid; row < RY * Cfg::RZ; row += NTH) {
+  // Points of the box per thread (staging and write-back).  For 9-point rows
+  // (TX = 4) a wavefront takes 7 whole rows per step, lane l point l mod 9 of
+  // row l / 9 (lane 63 idle): a thread's x offset and LDS slot are then fixed
+  // and its row advances by a constant, so the per-point index arithmetic
+  // becomes immediate offsets.  Otherwise thread t takes points t + NTH p.
+  constexpr int NROWS = RY * Cfg::RZ;
+  constexpr bool LANEMAP = RX == 9;
+  constexpr int RPI = LANEMAP ? 7 * (NTH / 64) : 1;  // rows per step of the lane map
+  constexpr int PF = LANEMAP ? (NROWS + RPI - 1) / RPI : (R + NTH - 1) / NTH;
+  constexpr int NSROW = LANEMAP ? PF * RPI : NROWS;  // row table padded to whole steps
+  const int lane63 = tid & 63, lq = lane63 < 63 ? lane63 / 9 : 0;
+  const int lrow = LANEMAP ? (tid >> 6) * 7 + lq : 0;
+  const int lx = LANEMAP ? (lane63 < 63 ? lane63 - 9 * lq : 16) : 0;  // 16: no point
+  // point p of this thread: its row and x, and whether it is a box point
+  auto point = [&](int p, int &row, int &rx) -> bool {
+    if constexpr (LANEMAP) {
+      row = lrow + RPI * p;
+      rx = lx;
+      return lx < RX && ((p + 1) * RPI <= NROWS || row < NROWS);
+    } else {
+      const int r = tid + p * NTH;
+      const int rc = r < R ? r : 0;
+      row = rc / RX;
+      rx = rc - row * RX;
+      return r < R;
+    }
+  };
+  __shared__ int2 srow[NSROW];
+  for (int row = tid; row < NSROW; row += NTH) {
+    if (row >= NROWS) {
+      srow[row] = make_int2(0, 1 << 22);  // padding: a row outside the macro
+      continue;
+    }
     const int ry = row % RY, rz = row / RY;
     const int qj = 2 * by0 + ry, qk = 2 * bz0 + rz;
     const int lim = N - qj - qk, L = lim - 2 * bx0;
@@ -1230,15 +1261,13 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
   // N1: the per-slot orientation signs (bytes) over the same block
   const __amdgpu_buffer_rsrc_t rss = __builtin_amdgcn_make_buffer_rsrc(
       Cfg::N1 ? const_cast<int8_t *>(D->sign + base) : nullptr, 0, Cfg::N1 ? D->L : 0, 0x00020000);
-  constexpr int PF = (R + NTH - 1) / NTH, NK = Cfg::NK;
+  constexpr int NK = Cfg::NK;
   T xv[PF][NCI], kv[PF][NK];
   int sgv[PF];
 #pragma unroll
   for (int p = 0; p < PF; ++p) {
-    const int r = tid + p * NTH;
-    const bool in = r < R;
-    const int rc = in ? r : 0;
-    const int row = rc / RX, rx = rc - row * RX;
+    int row, rx;
+    const bool in = point(p, row, rx);
     const int2 rw = srow[row];
     const uint32_t bits = static_cast<uint32_t>(rw.y);
     const bool kin = in && !((bits >> 22) & 1u) && rx <= static_cast<int>((bits >> 17) & 31u);
@@ -1264,9 +1293,8 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
   }
 #pragma unroll
   for (int p = 0; p < PF; ++p) {
-    const int r = tid + p * NTH;
-    if (r < R) {
-      const int row = r / RX, rx = r - row * RX;
+    int row, rx;
+    if (point(p, row, rx)) {
       const int sl = lds_slot(rx, row, OO, RXP);
 #pragma unroll
       for (int c = 0; c < NCI; ++c) sx[c][sl] = xv[p][c];
@@ -1342,11 +1370,16 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
     const __amdgpu_buffer_rsrc_t rsp = __builtin_amdgcn_make_buffer_rsrc(
         (a.partial ? a.partial : D->partial) + static_cast<int64_t>(tl.w) * NC * R, 0,
         NC * R * static_cast<int>(sizeof(T)), 0x00020000);
-    for (int r = tid; r < R; r += NTH) {
-      const int row = r / RX, rx = r - row * RX;
+    // (unrolled only for the lane map, where it turns the row steps into immediate offsets)
+    constexpr int WB_UNROLL = LANEMAP ? PF : 1;
+#pragma unroll WB_UNROLL
+    for (int p = 0; p < PF; ++p) {
+      int row, rx;
+      const bool in = point(p, row, rx);
+      const int r = row * RX + rx;
       const int2 rw = srow[row];
       const uint32_t bits = static_cast<uint32_t>(rw.y);
-      const bool valid = !((bits >> 22) & 1u) && rx <= static_cast<int>((bits >> 17) & 31u);
+      const bool valid = in && !((bits >> 22) & 1u) && rx <= static_cast<int>((bits >> 17) & 31u);
       const bool excl = ((bits >> 23) & 1u) && ((rx & 1) || ((rx > 0 || bx0 == 0) && rx < 2 * TX));
       // a point inside the macro whose x bit is clear is a Dirichlet DoF
       const bool dir = !Cfg::GRAD && !((bits >> rx) & 1u);
