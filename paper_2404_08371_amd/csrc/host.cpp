@@ -387,6 +387,39 @@ tmf_status upload_vec(DevBuf<uint8_t> &buf, const std::vector<T> &v) {
 
 }  // namespace
 
+namespace {
+// XCD (0..7) that runs tile ti of an element launch over ntiles tiles:
+// workgroups go round-robin over the 8 XCDs, and the element kernels give
+// XCD x the contiguous run of tiles from x q + min(x, r) (q, r = ntiles / 8, ntiles % 8)
+int tile_xcd(int ti, int ntiles) {
+  const int q = ntiles / 8, rem = ntiles % 8;
+  for (int x = 7; x > 0; --x)
+    if (ti >= x * q + std::min(x, rem)) return x;
+  return 0;
+}
+// seam work entries in launch order: entry i (counted from the first seam
+// entry, which starts at a multiple of 8) runs on XCD i mod 8, so it is given
+// an entry whose partial sums that XCD wrote where one is left (else one of
+// the XCD with the most left); each XCD's entries keep their order
+void seam_work_xcd(const std::vector<std::pair<int4, int>> &ent, std::vector<int4> &w) {
+  std::vector<int4> q[8];
+  for (const auto &e : ent) q[e.second].push_back(e.first);
+  size_t pos[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (size_t i = 0; i < ent.size(); ++i) {
+    int x = static_cast<int>(i % 8);
+    if (pos[x] == q[x].size()) {
+      size_t left = 0;
+      for (int y = 0; y < 8; ++y)
+        if (q[y].size() - pos[y] > left) {
+          left = q[y].size() - pos[y];
+          x = y;
+        }
+    }
+    w.push_back(q[x][pos[x]++]);
+  }
+}
+}  // namespace
+
 extern "C" {
 
 tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const double *qbary,
@@ -520,6 +553,7 @@ tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const
   if (st == TMF_OK && space == 2) {
     const int n = mesh->n, N = S.N;
     size_t partial_bytes = 0;
+    std::vector<std::pair<int4, int>> seam_entries[kNumTileCfg];
     for (int cfg = 0; cfg < kNumTileCfg && st == TMF_OK; ++cfg) {
       const int TX = kTileCfg[cfg][0], TY = kTileCfg[cfg][1], TZ = kTileCfg[cfg][2];
       // tiles, macro-major; .w = tile id within the operator
@@ -554,6 +588,21 @@ tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const
               pts.push_back(qx | (qy << 10) | (qz << 20));
       op->nseam[cfg] = static_cast<int>(pts.size());
       if (st == TMF_OK) st = op->seam[cfg].upload(pts.data(), pts.size());
+      // seam work entries and the XCD that wrote (most of) their partial sums:
+      // the one running the tile below the middle point of the entry's chunk
+      {
+        const int chunk = 256 * seam_ppt(op), ntl = static_cast<int>(tl.size());
+        for (int64_t mac = 0; mac < mesh->nt; ++mac)
+          for (int p0 = 0; p0 < static_cast<int>(pts.size()); p0 += chunk) {
+            const int pk = pts[std::min<size_t>(p0 + chunk / 2, pts.size() - 1)];
+            const int q[3] = {pk & 1023, (pk >> 10) & 1023, pk >> 20}, T3[3] = {TX, TY, TZ};
+            int b[3];
+            for (int d = 0; d < 3; ++d)
+              b[d] = (q[d] > 0 && q[d] % (2 * T3[d]) == 0) ? q[d] / 2 - T3[d] : T3[d] * (q[d] / (2 * T3[d]));
+            const int ti = static_cast<int>(mac) * id + rs[static_cast<size_t>(b[2] / TZ) * nby + b[1] / TY] + b[0] / TX;
+            seam_entries[cfg].push_back({make_int4(0, static_cast<int>(mac), p0, 0), tile_xcd(ti, ntl)});
+          }
+      }
       const size_t R = static_cast<size_t>(2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1);
       const size_t per_tile = R * op->ncomp * (prec == TMF_F64 ? 8 : 4);
       op->partial_bytes[cfg] = tl.size() * per_tile;
@@ -608,8 +657,11 @@ tmf_status tmf_op_create(const tmf_mesh *mesh, int kind, int prec, int bc, const
       // the bulk of the seam points instead of forming the launch's tail
       std::vector<int4> w;
       group_work(op, 0, w);
+      // (padded with empty group entries to a multiple of 8, so that the
+      // seam entries keep their XCD whether or not the groups are launched)
+      while (w.size() % 8 != 0) w.push_back(make_int4(0, 0, 0, 1));
       op->ngroupwork[cfg] = static_cast<int>(w.size());
-      seam_work(op, cfg, 0, w);
+      seam_work_xcd(seam_entries[cfg], w);
       op->nseamwork[cfg] = static_cast<int>(w.size());
       op->nseamonly[cfg] = op->nseamwork[cfg] - op->ngroupwork[cfg];
       if (st == TMF_OK) st = op->seamwork[cfg].upload(w.data(), w.size());
