@@ -1431,24 +1431,35 @@ __device__ __forceinline__ void seam_sum(const SeamInst<T> &a, RS rs, GPtr<const
   constexpr int RX = 2 * TX + 1, RY = 2 * TY + 1, R = RX * RY * (2 * TZ + 1);
   auto lower = [](int q, int t) { return (q > 0 && q % (2 * t) == 0) ? q / 2 - t : t * (q / (2 * t)); };
   const int x0 = lower(qx, TX), y0 = lower(qy, TY), z0 = lower(qz, TZ);
-  const int nx = (qx > 0 && qx % (2 * TX) == 0) ? 2 : 1;
-  const int ny = (qy > 0 && qy % (2 * TY) == 0) ? 2 : 1;
-  const int nz = (qz > 0 && qz % (2 * TZ) == 0) ? 2 : 1;
+  const bool fx = qx > 0 && qx % (2 * TX) == 0, fy = qy > 0 && qy % (2 * TY) == 0, fz = qz > 0 && qz % (2 * TZ) == 0;
   // a candidate's loads are issued only where it exists (a wavefront of face
   // points skips the candidates across the other two faces), and none of the
   // loads is used before all are issued, so they are in flight together; a
   // missing candidate adds +0, which leaves the sum (started at +0) unchanged.
-  // The tile-row lookups come first, for every candidate (entry 0 where it
-  // does not exist), so they too are in flight together.
+  // Candidate e = (ix, iy, iz) is the box (x0 + ix TX, y0 + iy TY, z0 + iz TZ)
+  // in tile row (iy, iz): the up to 4 row lookups come first (entry 0 for a
+  // row without a candidate box), so they are in flight together; within a
+  // row the tile id advances by ix, and the box-local point index falls by
+  // 2 TX ix + 2 TY RX iy + 2 TZ RX RY iz.
+  const int s0 = x0 + y0 + z0;
+  const int rbase = (z0 / TZ) * a.nby + y0 / TY;
+  const uint32_t r0 = static_cast<uint32_t>((qx - 2 * x0) + RX * ((qy - 2 * y0) + RY * (qz - 2 * z0)));
+  int rowt[4];
+  bool rowok[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int iy = j & 1, iz = j >> 1;
+    rowok[j] = (!iy || fy) && (!iz || fz) && s0 + iy * TY + iz * TZ <= a.n - 1;
+    rowt[j] = rs[rowok[j] ? rbase + iz * a.nby + iy : 0] + x0 / TX;
+  }
   uint32_t boff[8];
   bool ok[8];
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const int ix = e & 1, iy = (e >> 1) & 1, iz = e >> 2;
-    const int bx = x0 + ix * TX, by = y0 + iy * TY, bz = z0 + iz * TZ;
-    ok[e] = ix < nx && iy < ny && iz < nz && bx + by + bz <= a.n - 1;
-    const uint32_t tile = static_cast<uint32_t>(rs[ok[e] ? (bz / TZ) * a.nby + by / TY : 0] + bx / TX);
-    const uint32_t r = static_cast<uint32_t>((qx - 2 * bx) + RX * ((qy - 2 * by) + RY * (qz - 2 * bz)));
+    ok[e] = rowok[iy + 2 * iz] && (!ix || fx) && s0 + ix * TX + iy * TY + iz * TZ <= a.n - 1;
+    const uint32_t tile = static_cast<uint32_t>(rowt[iy + 2 * iz] + ix);
+    const uint32_t r = r0 - static_cast<uint32_t>(2 * TX * ix + 2 * TY * RX * iy + 2 * TZ * RX * RY * iz);
     boff[e] = (tile * (NC * R) + r) * static_cast<uint32_t>(sizeof(T));
   }
   T v[8][NC];
