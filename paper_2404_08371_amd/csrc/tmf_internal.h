@@ -210,7 +210,7 @@ struct SeamInst {
 constexpr int kSeamRowsLds = 8192;
 // seam points per thread of the seam reduction for scalar fields (vector
 // fields: 1); a seam work entry covers 256 times this many points
-constexpr int kSeamPointsPerThread = 4;
+constexpr int kSeamPointsPerThread = 2;
 
 // launchers (kernels.hip); return the HIP error of the launch
 template <typename T>
