@@ -1089,7 +1089,12 @@ __device__ __forceinline__ bool cube_elem(const TileArgs<T> &a, const InstDesc<T
   using Cfg = TileCfg<T, KIND, MAP, TX, TY, TZ>;
   constexpr int RY = Cfg::RY, OO = Cfg::OO, RXP = Cfg::RXP;
   const int cx = c % TX, cy = (c / TX) % TY, cz = c / (TX * TY);
-  if (c >= Cfg::C || bx0 + by0 + bz0 + cx + cy + cz > D->n - kLim[t]) return false;
+  const bool exists = c < Cfg::C && bx0 + by0 + bz0 + cx + cy + cz <= D->n - kLim[t];
+  // scalar P2 applies compute every lane's micro-tet (its nodes lie in the
+  // staged box either way, and a missing one is not added): no branch around
+  // the element code and no defined results needed on a skipped path
+  constexpr bool ALWAYS = KIND == P2_LAPLACE || KIND == P2_DIVKGRAD;
+  if (!ALWAYS && !exists) return false;
   const int cb = cx + RXP * (2 * cy + RY * 2 * cz);
   cbo = cb;
   int li[10];
@@ -1103,7 +1108,7 @@ __device__ __forceinline__ bool cube_elem(const TileArgs<T> &a, const InstDesc<T
     me.off = c * static_cast<int>(sizeof(T));
   }
   tile_elem<T, KIND, MAP, R, t, Cfg::C>(a, D, sx, sk, out, li, m, bx0 + cx, by0 + cy, bz0 + cz, me);
-  return true;
+  return exists;
 }
 
 // add a micro-tet's local results (cube_elem) into the LDS accumulator
