@@ -1189,8 +1189,9 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
   // 0. the box's lattice rows (qj, qk): {offset in the macro block of the
   // row's first box point (qi = 2 bx0), bits}: bits 0 .. RX-1 mark the box
   // points whose x is staged (inside the macro and not a Dirichlet DoF), bits
-  // 17 .. 21 hold the last box point inside the macro (khi), bit 22 is set for
-  // a row outside the macro and bit 23 for a row this box owns in y and z
+  // 17 .. 21 hold the number of the row's box points inside the macro (khi + 1,
+  // 0 for a row outside it), bit 22 is set for a row outside the macro and bit
+  // 23 for a row this box owns in y and z
   // (write-back).  A point's Dirichlet test by its face pattern is folded into
   // the row: within a row only the two end points can differ from the rest.
   static_assert(RX <= 17, "the row masks hold at most 17 points");
@@ -1243,7 +1244,7 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
     const bool ey = (ry & 1) || ((ry > 0 || by0 == 0) && ry < 2 * TY);
     const bool ez = (rz & 1) || ((rz > 0 || bz0 == 0) && rz < 2 * TZ);
     srow[row] = make_int2(empty ? 0 : row_base(qj, qk, N) + 2 * bx0,
-                          static_cast<int>(xmask | (uint32_t(khi) << 17) | (uint32_t(empty) << 22) |
+                          static_cast<int>(xmask | (uint32_t(empty ? 0 : khi + 1) << 17) | (uint32_t(empty) << 22) |
                                            (uint32_t(ey && ez) << 23)));
   }
   __syncthreads();
@@ -1275,8 +1276,10 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
     const bool in = point(p, row, rx);
     const int2 rw = srow[row];
     const uint32_t bits = static_cast<uint32_t>(rw.y);
-    const bool kin = in && !((bits >> 22) & 1u) && rx <= static_cast<int>((bits >> 17) & 31u);
-    const bool xin = in && ((bits >> rx) & 1u);
+    // (with the lane map, the padding rows and the idle lane 63, x = 16, fail
+    // both tests by themselves: no point count or x bit reaches them)
+    const bool kin = (LANEMAP || in) && rx < static_cast<int>((bits >> 17) & 31u);
+    const bool xin = (LANEMAP || in) && ((bits >> rx) & 1u);
     const int off = rw.x + rx;
 #pragma unroll
     for (int c = 0; c < NCI; ++c)
@@ -1384,7 +1387,7 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
       const int r = row * RX + rx;
       const int2 rw = srow[row];
       const uint32_t bits = static_cast<uint32_t>(rw.y);
-      const bool valid = in && !((bits >> 22) & 1u) && rx <= static_cast<int>((bits >> 17) & 31u);
+      const bool valid = (LANEMAP || in) && rx < static_cast<int>((bits >> 17) & 31u);
       const bool excl = ((bits >> 23) & 1u) && ((rx & 1) || ((rx > 0 || bx0 == 0) && rx < 2 * TX));
       // a point inside the macro whose x bit is clear is a Dirichlet DoF
       const bool dir = !Cfg::GRAD && !((bits >> rx) & 1u);
