@@ -1189,11 +1189,11 @@ __global__ __launch_bounds__((TileCfg<T, KIND, MAP, TX, TY, TZ>::NTH)) void k_ti
   // 0. the box's lattice rows (qj, qk): {offset in the macro block of the
   // row's first box point (qi = 2 bx0), bits}: bits 0 .. RX-1 mark the box
   // points whose x is staged (inside the macro and not a Dirichlet DoF), bits
-  // 17 .. 21 hold the number of the row's box points inside the macro (khi + 1,
+  // 17 .. 21 hold the number of the row's box points inside the macro (khi + 1;
   // 0 for a row outside it), bit 22 is set for a row outside the macro and bit
-  // 23 for a row this box owns in y and z
-  // (write-back).  A point's Dirichlet test by its face pattern is folded into
-  // the row: within a row only the two end points can differ from the rest.
+  // 23 for a row this box owns in y and z (write-back).  A point's Dirichlet
+  // test by its face pattern is folded into the row: within a row only the two
+  // end points can differ from the rest.
   static_assert(RX <= 17, "the row masks hold at most 17 points");
   // Points of the box per thread (staging and write-back).  For 9-point rows
   // (TX = 4) a wavefront takes 7 whole rows per step, lane l point l mod 9 of
