@@ -1092,7 +1092,9 @@ __device__ __forceinline__ bool cube_elem(const TileArgs<T> &a, const InstDesc<T
   const bool exists = c < Cfg::C && bx0 + by0 + bz0 + cx + cy + cz <= D->n - kLim[t];
   // scalar P2 applies compute every lane's micro-tet (its nodes lie in the
   // staged box either way, and a missing one is not added): no branch around
-  // the element code and no defined results needed on a skipped path
+  // the element code and no defined results needed on a skipped path.  Their
+  // cube index is always below C: the lane (64-cube boxes, three wavefronts)
+  // or lane + 64 r (128-cube boxes, six wavefronts).
   constexpr bool ALWAYS = KIND == P2_LAPLACE || KIND == P2_DIVKGRAD;
   if (!ALWAYS && !exists) return false;
   const int cb = cx + RXP * (2 * cy + RY * 2 * cz);
